@@ -1,0 +1,190 @@
+"""FP64 CPU oracle (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use
+this package.  It wraps ``nnp_oracle.c`` (plain C, IEEE double, OpenMP over
+atoms) through ctypes and shares nothing with the HIP path.  Every function
+operates on ONE molecule; callers loop over molecules of a batch.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nnp_oracle.c")
+_SO = os.path.join(_HERE, "libnnp_oracle.so")
+_lib = None
+
+NFEAT = 384
+RC_RAD = 5.2
+RC_ANG = 3.5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE semantics: no fast-math)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build(force=False)
+    lib = ctypes.CDLL(_SO)
+    P = ctypes.POINTER
+    d, i, f = ctypes.c_double, ctypes.c_int, ctypes.c_float
+    lib.oracle_pairs.restype = ctypes.c_long
+    lib.oracle_pairs.argtypes = [i, P(d), d, P(i), P(i), ctypes.c_long]
+    lib.oracle_descriptors.restype = None
+    lib.oracle_descriptors.argtypes = [i, P(d), P(i), P(d)]
+    lib.oracle_mlp.restype = None
+    lib.oracle_mlp.argtypes = [i, P(f), P(d), P(d), P(d)]
+    lib.oracle_energy_forces.restype = d
+    lib.oracle_energy_forces.argtypes = [i, P(d), P(i), P(f), P(d), P(d)]
+    lib.oracle_forces_on.restype = None
+    lib.oracle_forces_on.argtypes = [i, P(d), P(i), P(f), i, P(i), P(d)]
+    lib.oracle_vv.restype = None
+    lib.oracle_vv.argtypes = [i, P(d), P(d), P(d), P(i), P(f), i, d, i, P(d), P(d)]
+    lib.oracle_threads.restype = i
+    lib.oracle_threads.argtypes = []
+    lib.oracle_set_threads.restype = None
+    lib.oracle_set_threads.argtypes = [i]
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _pos(p):
+    return np.ascontiguousarray(p, dtype=np.float64).reshape(-1, 3)
+
+
+def _sp(s):
+    return np.ascontiguousarray(s, dtype=np.int32)
+
+
+def _w(w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    return w
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def set_threads(t: int) -> None:
+    _load().oracle_set_threads(int(t))
+
+
+def pairs(pos, rc: float) -> np.ndarray:
+    """Ordered pairs (i, j), i != j, r_ij < rc, lexicographic; shape (P, 2)."""
+    lib = _load()
+    p = _pos(pos)
+    n = p.shape[0]
+    cnt = lib.oracle_pairs(n, _ptr(p, ctypes.c_double), rc, None, None, 0)
+    oi = np.empty(max(cnt, 1), np.int32)
+    oj = np.empty(max(cnt, 1), np.int32)
+    lib.oracle_pairs(n, _ptr(p, ctypes.c_double), rc, _ptr(oi, ctypes.c_int),
+                     _ptr(oj, ctypes.c_int), cnt)
+    return np.stack([oi[:cnt], oj[:cnt]], axis=1)
+
+
+def descriptors(pos, species) -> np.ndarray:
+    lib = _load()
+    p, s = _pos(pos), _sp(species)
+    G = np.zeros((p.shape[0], NFEAT), np.float64)
+    lib.oracle_descriptors(p.shape[0], _ptr(p, ctypes.c_double), _ptr(s, ctypes.c_int),
+                           _ptr(G, ctypes.c_double))
+    return G
+
+
+def mlp(element: int, weights, G) -> Tuple[float, np.ndarray]:
+    """Energy of one atom and its gradient with respect to the 384 features."""
+    lib = _load()
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    E = np.zeros(1, np.float64)
+    g = np.zeros(NFEAT, np.float64)
+    w = _w(weights)
+    lib.oracle_mlp(int(element), _ptr(w, ctypes.c_float), _ptr(G, ctypes.c_double),
+                   _ptr(E, ctypes.c_double), _ptr(g, ctypes.c_double))
+    return float(E[0]), g
+
+
+def energy_forces(pos, species, weights, forces: bool = True):
+    """Returns (E, E_i[n], F[n,3] or None) for one molecule."""
+    lib = _load()
+    p, s, w = _pos(pos), _sp(species), _w(weights)
+    n = p.shape[0]
+    Ei = np.zeros(n, np.float64)
+    F = np.zeros((n, 3), np.float64) if forces else None
+    E = lib.oracle_energy_forces(n, _ptr(p, ctypes.c_double), _ptr(s, ctypes.c_int),
+                                 _ptr(w, ctypes.c_float), _ptr(Ei, ctypes.c_double),
+                                 _ptr(F, ctypes.c_double) if forces else None)
+    return float(E), Ei, F
+
+
+def forces_on(pos, species, weights, sel) -> np.ndarray:
+    lib = _load()
+    p, s, w = _pos(pos), _sp(species), _w(weights)
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    F = np.zeros((sel.shape[0], 3), np.float64)
+    lib.oracle_forces_on(p.shape[0], _ptr(p, ctypes.c_double), _ptr(s, ctypes.c_int),
+                         _ptr(w, ctypes.c_float), sel.shape[0], _ptr(sel, ctypes.c_int),
+                         _ptr(F, ctypes.c_double))
+    return F
+
+
+def vv(pos, vel, masses, species, weights, dt: float, nsteps: int, model: int = 0):
+    """NVE velocity Verlet.  Returns (x, v, U[nsteps+1], K[nsteps+1])."""
+    lib = _load()
+    x = _pos(pos).copy()
+    v = _pos(vel).copy()
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    s = _sp(species)
+    w = _w(weights) if weights is not None else np.zeros(1, np.float32)
+    U = np.zeros(nsteps + 1, np.float64)
+    K = np.zeros(nsteps + 1, np.float64)
+    lib.oracle_vv(x.shape[0], _ptr(x, ctypes.c_double), _ptr(v, ctypes.c_double),
+                  _ptr(m, ctypes.c_double), _ptr(s, ctypes.c_int), _ptr(w, ctypes.c_float),
+                  int(model), float(dt), int(nsteps), _ptr(U, ctypes.c_double),
+                  _ptr(K, ctypes.c_double))
+    return x, v, U, K
+
+
+def local_environment(pos, centre: int, radius: float) -> np.ndarray:
+    """Indices (ascending) of atoms closer than ``radius`` to atom ``centre``,
+    the centre included.  Any quantity of the centre that depends only on
+    atoms within that radius is reproduced exactly on this subset."""
+    p = _pos(pos)
+    d = np.sqrt(((p - p[centre]) ** 2).sum(axis=1))
+    return np.nonzero(d < radius)[0].astype(np.int64)
+
+
+def system_energy_forces(system, forces: bool = True):
+    """Per-molecule energies (M,), per-atom energies (N,), forces (N,3)."""
+    M = system.n_molecules
+    E = np.zeros(M)
+    Ei = np.zeros(system.n_atoms)
+    F = np.zeros((system.n_atoms, 3)) if forces else None
+    for m in range(M):
+        s = system.molecule(m)
+        e, ei, f = energy_forces(system.pos[s], system.species[s], system.weights, forces)
+        E[m] = e
+        Ei[s] = ei
+        if forces:
+            F[s] = f
+    return E, Ei, F

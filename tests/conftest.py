@@ -1,0 +1,32 @@
+import functools
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@functools.lru_cache(maxsize=None)
+def _system(name):
+    import synth
+    return synth.make_config(name)
+
+
+@pytest.fixture(scope="session")
+def make_system():
+    return _system
+
+
+@pytest.fixture(scope="session")
+def oracle_lib():
+    import oracle
+    oracle._load()
+    return oracle
