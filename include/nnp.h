@@ -1,0 +1,206 @@
+/*
+ * nnp.h -- C ABI of the MI355X (gfx950) gas-phase NNP energy/force/MD library.
+ *
+ * The library implements the force-provider contract of the paper (Methods
+ * section: a model object registered with the MD engine, called with the
+ * positions, returning the potential energy, with the forces obtained as
+ * minus its gradient; the explicit-force provider variant returns both):
+ *
+ *     nnp_create(params)  ->  nnp_compute(positions, box)  ->  energy, forces
+ *                         ->  nnp_step(dt, n)              (NVE velocity Verlet)
+ *
+ * The model is a symmetry-function network potential:
+ *   - pair sets within 5.2 A (radial) and 3.5 A (angular), gas phase (no box);
+ *   - 64 radial features (16 Gaussians, eta = 16 A^-2, centres 0.9..5.1 A, cosine
+ *     cutoff 5.2 A, per neighbour element) and 320 angular features (4 shells x 8
+ *     sectors, zeta = 32, cosine cutoff 3.5 A, per unordered element pair);
+ *   - per-element network 384 -> 160 -> 128 -> 96 -> 1 with CELU(alpha = 0.1);
+ *   - E = sum_i E_i, forces F = -dE/dx by a hand-written adjoint;
+ *   - FP64 energy reduction and FP64 velocity Verlet (the paper's engine keeps
+ *     integration in higher precision than the model, Results section).
+ *
+ * Units: Angstrom, fs, amu, eV.  Elements: 0 = H, 1 = C, 2 = N, 3 = O.
+ *
+ * Ownership: the caller owns every array it passes.  Host arrays are copied
+ * during the call; no caller pointer is retained after a call returns (the
+ * paper's keep-alive rule for the registered model object is replaced by the
+ * opaque context, which the caller keeps until nnp_destroy).  The context owns
+ * all device memory, streams it created, and captured graphs.  Functions that
+ * take device pointers borrow them for the duration of the work they enqueue
+ * on the context stream.
+ *
+ * Errors: every call returns an nnp_status; no C++ exception crosses this
+ * boundary.  Arguments are validated on the host before any device work; a
+ * failed validation leaves the context unchanged.  nnp_last_error() gives a
+ * per-context message for the most recent failure.
+ *
+ * Threading: a context may be used by one host thread at a time; distinct
+ * contexts are independent.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnp_context nnp_context;
+
+typedef enum {
+    NNP_OK = 0,
+    NNP_ERR_ARG = 1,         /* invalid argument (NULL, out of range, size mismatch) */
+    NNP_ERR_NONFINITE = 2,   /* NaN/Inf input, coincident atoms, or non-finite result */
+    NNP_ERR_UNSUPPORTED = 3, /* valid request the library does not implement (e.g. a box) */
+    NNP_ERR_OOM = 4,         /* device allocation failed */
+    NNP_ERR_HIP = 5,         /* HIP runtime error; message holds the HIP error string */
+    NNP_ERR_STATE = 6        /* call not valid in the current state, or a device-side
+                                capacity overflow (neighbour list, LDS environment) */
+} nnp_status;
+
+/* What nnp_compute returns (the paper's Callable return flag: energy only,
+ * forces then come from differentiation; or energy and explicit forces). */
+typedef enum { NNP_RETURN_ENERGY = 1, NNP_RETURN_ENERGY_FORCES = 3 } nnp_return;
+
+/* Arithmetic of the network GEMMs.  Descriptors and the adjoint are FP32 in
+ * every mode; energy reduction and integration are FP64.
+ *   NNP_MLP_FP32        FP32 FMA on the vector ALUs;
+ *   NNP_MLP_BF16        BF16 MFMA, FP32 accumulation, one product per GEMM;
+ *   NNP_MLP_FP8         OCP E4M3 MFMA with per-layer scales (not available);
+ *   NNP_MLP_BF16_SPLIT  BF16 MFMA on split operands: each FP32 weight and
+ *                       activation x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
+ *                       hi*hi + hi*lo + lo*hi, FP32 accumulation (three MFMAs). */
+typedef enum { NNP_MLP_FP32 = 0, NNP_MLP_BF16 = 1, NNP_MLP_FP8 = 2, NNP_MLP_BF16_SPLIT = 3 } nnp_dtype;
+
+/* Kernel organisation of one energy/force evaluation.
+ *   NNP_PATH_PLAIN: one kernel per stage (pair list, descriptors, network,
+ *                   adjoint), descriptors and dE/dG round-trip through HBM;
+ *   NNP_PATH_FUSED: one kernel per evaluation; a workgroup takes a tile of
+ *                   atoms of one element through descriptors, network and
+ *                   adjoint with every intermediate held in LDS. */
+typedef enum { NNP_PATH_PLAIN = 0, NNP_PATH_FUSED = 1 } nnp_path;
+
+typedef struct {
+    int32_t n_atoms;             /* total atoms over all molecules, > 0 */
+    int32_t n_molecules;         /* >= 1; molecules never interact */
+    const int32_t* mol_offsets;  /* [n_molecules + 1], molecule m = atoms
+                                    [off[m], off[m+1]); NULL allowed iff n_molecules == 1 */
+    const int32_t* species;      /* [n_atoms], each in {0, 1, 2, 3} */
+    const double* masses;        /* [n_atoms] amu, each > 0 */
+    const float* weights;        /* network blob, float32, per element H, C, N, O:
+                                    W1[160][384] b1[160] W2[128][160] b2[128]
+                                    W3[96][128] b3[96] W4[1][96] b4[1] */
+    size_t weights_count;        /* number of floats in the blob (4 * 94689) */
+    nnp_dtype mlp_dtype;
+    nnp_path path;
+    int32_t rebuild_every;       /* pair-list rebuild cadence in steps (e.g. 20), >= 1 */
+    double skin;                 /* pair-list skin in A (e.g. 1.0), >= 0 */
+    int32_t max_neighbors;       /* capacity of one atom's pair list (cutoff 5.2 + skin),
+                                    <= 256; 0 selects 192 */
+    int32_t atoms_per_tile;      /* atoms per workgroup: 4 or 8 (fused path), 8 or 16
+                                    (plain path); 0 selects 8 (fused) or 16 (plain) */
+    void* stream;                /* hipStream_t to run on, or NULL for a stream owned by
+                                    the context */
+} nnp_params;
+
+/* Creates a context: validates params, sorts atoms into the internal order,
+ * uploads weights and allocates every device buffer.  Positions and velocities
+ * start at zero; call nnp_set_state or nnp_compute before nnp_step. */
+nnp_status nnp_create(const nnp_params* params, nnp_context** out);
+
+/* Releases the context and every device resource it owns.  NULL is a no-op. */
+void nnp_destroy(nnp_context* ctx);
+
+/* Energy (and forces) at the given positions (the force-provider call).
+ *   pos     host [n_atoms][3] double, caller order.  Must be finite, no two
+ *           atoms of one molecule closer than 1e-6 A (else NNP_ERR_NONFINITE);
+ *   box     must be NULL (gas phase; a periodic box is NNP_ERR_UNSUPPORTED);
+ *   energy  host [n_molecules] double, molecule potential energies (eV);
+ *   forces  host [n_atoms][3] double (eV/A), or NULL for energy only.
+ * The positions become the context's current positions (velocities are kept);
+ * the pair list is rebuilt.  Synchronises the context stream. */
+nnp_status nnp_compute(nnp_context* ctx, const double* pos, const double* box, double* energy,
+                       double* forces);
+
+/* Device-pointer form used by the PyTorch binding (autograd).  All pointers are
+ * device memory, caller order, enqueued on the context stream, no host sync:
+ *   d_pos     [n_atoms][3]; d_pos_is_f64 selects double (1) or float (0);
+ *   d_energy  [n_molecules] double (written);
+ *   d_forces  [n_atoms][3] double, or NULL for energy only (then the network
+ *             backward and the adjoint are skipped).
+ * No host-side validation of the device positions is possible; a non-finite
+ * result is reported by the next host-synchronising call. */
+nnp_status nnp_compute_device(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy,
+                              double* d_forces);
+
+/* Sets positions and velocities (host [n_atoms][3] double, caller order;
+ * either may be NULL to keep the current value). Forces are recomputed lazily. */
+nnp_status nnp_set_state(nnp_context* ctx, const double* pos, const double* vel);
+
+/* Copies the current state to the host.  Any pointer may be NULL.
+ *   pos, vel, forces  [n_atoms][3] double, caller order;
+ *   pot, kin          [n_molecules] double: potential and kinetic energy of the
+ *                     most recent evaluated step.  Synchronises. */
+nnp_status nnp_get_state(nnp_context* ctx, double* pos, double* vel, double* forces, double* pot,
+                         double* kin);
+
+/* Advances n_steps of NVE velocity Verlet with time step dt_fs:
+ *   v += dt/2 kappa F/m;  x += dt v;  F = F(x);  v += dt/2 kappa F/m,
+ * kappa = 9.64853321e-3 A fs^-2 per eV A^-1 amu^-1.  The pair list is rebuilt
+ * every rebuild_every steps, and earlier when an atom moved more than skin/2
+ * since the last rebuild (decided on the device; counted in nnp_stats).
+ * use_graph != 0 replays the steps from a captured HIP graph (captured on
+ * first use for the given block length and dt).  Returns after enqueueing;
+ * nnp_get_state / nnp_energy_log synchronise. */
+nnp_status nnp_step(nnp_context* ctx, double dt_fs, int32_t n_steps, int32_t use_graph);
+
+/* Potential and kinetic energy of the last min(count, steps done, ring size)
+ * steps, oldest first: U and K are [count][n_molecules] double.  Returns the
+ * number of steps written in *written.  The ring holds 4096 steps. */
+nnp_status nnp_energy_log(nnp_context* ctx, int32_t count, double* U, double* K, int32_t* written);
+
+/* Counters since creation: [0] evaluations, [1] pair-list rebuilds, [2] rebuilds
+ * forced by displacement > skin/2, [3] steps, [4] longest pair list, [5] most
+ * neighbours within 5.2 A, [6] most neighbours within 3.5 A (capacities: 256,
+ * 160 and 96 per atom; exceeding one makes the next synchronising call return
+ * NNP_ERR_STATE).  stats is int64[7]. */
+nnp_status nnp_stats(nnp_context* ctx, int64_t* stats);
+
+/* Descriptors at the given host positions, for parity checks: G is host
+ * [n_atoms][384] float, caller order.  Synchronises. */
+nnp_status nnp_debug_descriptors(nnp_context* ctx, const double* pos, float* G);
+
+/* Per-atom energies E_i (host [n_atoms] double, caller order) of the most
+ * recent evaluation.  Synchronises. */
+nnp_status nnp_debug_atom_energies(nnp_context* ctx, double* Ei);
+
+/* Bytes of device memory the context holds (buffers, weights, graphs' inputs). */
+nnp_status nnp_device_bytes(nnp_context* ctx, int64_t* bytes);
+
+/* Times the candidate launch configurations (atoms per workgroup) on the
+ * current positions and keeps the fastest; if cache_path is not NULL the
+ * choice is read from / appended to that JSON-lines file, keyed by atom
+ * count bucket, molecule count, path and dtype.  Synchronises. */
+nnp_status nnp_autotune(nnp_context* ctx, const char* cache_path);
+
+/* Kernel timing on the context stream with HIP events, at the current
+ * positions: runs one evaluation to make the pair list current, then times
+ * reps back-to-back launches of the evaluation kernel(s) alone (the pair
+ * list is not rebuilt during them) and reps launches of the force-gather /
+ * energy kernel alone.  ms[0] and ms[1] receive the average milliseconds per
+ * launch of each.  Used by the benchmark's roofline report.  Synchronises. */
+nnp_status nnp_time_kernels(nnp_context* ctx, int32_t reps, double* ms);
+
+/* Message for the most recent failure on this context ("" if none). */
+const char* nnp_last_error(const nnp_context* ctx);
+
+/* Static name of a status code. */
+const char* nnp_status_string(nnp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNP_H */

@@ -1,0 +1,92 @@
+"""ctypes declarations of the C ABI in include/nnp.h (argument marshalling only).
+
+Loading fails loudly when the HIP library has not been built: there is no
+CPU fallback of any kind.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnnp_hip.so")
+
+NNP_OK = 0
+STATUS_NAMES = {0: "NNP_OK", 1: "NNP_ERR_ARG", 2: "NNP_ERR_NONFINITE", 3: "NNP_ERR_UNSUPPORTED",
+                4: "NNP_ERR_OOM", 5: "NNP_ERR_HIP", 6: "NNP_ERR_STATE"}
+DTYPES = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
+PATHS = {"plain": 0, "fused": 1}
+
+#: Every function the header declares.
+EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nnp_set_state",
+           "nnp_get_state", "nnp_step", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
+           "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels",
+           "nnp_last_error", "nnp_status_string")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int32),
+        ("n_molecules", ctypes.c_int32),
+        ("mol_offsets", ctypes.POINTER(ctypes.c_int32)),
+        ("species", ctypes.POINTER(ctypes.c_int32)),
+        ("masses", ctypes.POINTER(ctypes.c_double)),
+        ("weights", ctypes.POINTER(ctypes.c_float)),
+        ("weights_count", ctypes.c_size_t),
+        ("mlp_dtype", ctypes.c_int),
+        ("path", ctypes.c_int),
+        ("rebuild_every", ctypes.c_int32),
+        ("skin", ctypes.c_double),
+        ("max_neighbors", ctypes.c_int32),
+        ("atoms_per_tile", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class NNPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+        self.message = message
+
+
+_lib = None
+
+
+def load():
+    """Loads libnnp_hip.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("HIP library %s is not built; run `python -m paper_2412_18271_amd.build`"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, d, i32, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+    st = ctypes.c_int
+    sig = {
+        "nnp_create": (st, [P(Params), P(vp)]),
+        "nnp_destroy": (None, [vp]),
+        "nnp_compute": (st, [vp, P(d), P(d), P(d), P(d)]),
+        "nnp_compute_device": (st, [vp, vp, ctypes.c_int, vp, vp]),
+        "nnp_set_state": (st, [vp, P(d), P(d)]),
+        "nnp_get_state": (st, [vp, P(d), P(d), P(d), P(d), P(d)]),
+        "nnp_step": (st, [vp, d, i32, i32]),
+        "nnp_energy_log": (st, [vp, i32, P(d), P(d), P(i32)]),
+        "nnp_stats": (st, [vp, P(i64)]),
+        "nnp_debug_descriptors": (st, [vp, P(d), P(ctypes.c_float)]),
+        "nnp_debug_atom_energies": (st, [vp, P(d)]),
+        "nnp_device_bytes": (st, [vp, P(i64)]),
+        "nnp_autotune": (st, [vp, ctypes.c_char_p]),
+        "nnp_time_kernels": (st, [vp, i32, P(d)]),
+        "nnp_last_error": (ctypes.c_char_p, [vp]),
+        "nnp_status_string": (ctypes.c_char_p, [st]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib

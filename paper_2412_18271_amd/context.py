@@ -1,0 +1,164 @@
+"""Python handle on one library context (names follow the C ABI)."""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import NNPError
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+class Context:
+    """Wraps nnp_create .. nnp_destroy.
+
+    species, masses, weights and mol_offsets are copied by the library at
+    creation.  ``stream`` is a raw hipStream_t (int) or None for a stream the
+    context owns.
+    """
+
+    def __init__(self, species, masses, weights, mol_offsets=None, dtype: str = "fp32",
+                 path: str = "fused", rebuild_every: int = 20, skin: float = 1.0,
+                 max_neighbors: int = 0, atoms_per_tile: int = 0, stream: Optional[int] = None):
+        self._lib = _lib.load()
+        self._sp = np.ascontiguousarray(species, dtype=np.int32)
+        self._m = np.ascontiguousarray(masses, dtype=np.float64)
+        self._w = np.ascontiguousarray(weights, dtype=np.float32)
+        n = int(self._sp.shape[0])
+        if mol_offsets is None:
+            self._off = np.array([0, n], dtype=np.int32)
+        else:
+            self._off = np.ascontiguousarray(mol_offsets, dtype=np.int32)
+        self.n_atoms = n
+        self.n_molecules = int(self._off.shape[0] - 1)
+        self.dtype = dtype
+        self.path = path
+        p = _lib.Params()
+        p.n_atoms = n
+        p.n_molecules = self.n_molecules
+        p.mol_offsets = self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        p.species = self._sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        p.masses = self._m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.weights = self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        p.weights_count = int(self._w.shape[0])
+        p.mlp_dtype = _lib.DTYPES[dtype]
+        p.path = _lib.PATHS[path]
+        p.rebuild_every = int(rebuild_every)
+        p.skin = float(skin)
+        p.max_neighbors = int(max_neighbors)
+        p.atoms_per_tile = int(atoms_per_tile)
+        p.stream = stream
+        h = ctypes.c_void_p()
+        s = self._lib.nnp_create(ctypes.byref(p), ctypes.byref(h))
+        if s != _lib.NNP_OK:
+            raise NNPError(s, "nnp_create failed (message on stderr)")
+        self._h = h
+
+    @classmethod
+    def from_system(cls, system, **kw):
+        return cls(system.species, system.masses, system.weights, system.mol_offsets, **kw)
+
+    # ------------------------------------------------------------------
+    def _check(self, s):
+        if s != _lib.NNP_OK:
+            msg = self._lib.nnp_last_error(self._h)
+            raise NNPError(s, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.nnp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def _pos(self, pos):
+        p = np.ascontiguousarray(pos, dtype=np.float64).reshape(self.n_atoms, 3)
+        return p
+
+    def compute(self, pos, forces: bool = True, box=None):
+        """Energies per molecule (M,) and forces (N, 3) (None if not asked)."""
+        p = self._pos(pos)
+        E = np.zeros(self.n_molecules, np.float64)
+        F = np.zeros((self.n_atoms, 3), np.float64) if forces else None
+        b = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+        self._check(self._lib.nnp_compute(self._h, _dptr(p), _dptr(b), _dptr(E), _dptr(F)))
+        return E, F
+
+    def compute_device(self, d_pos: int, pos_is_f64: bool, d_energy: int, d_forces: Optional[int]):
+        """Raw device-pointer evaluation on the context stream (no sync)."""
+        self._check(self._lib.nnp_compute_device(self._h, ctypes.c_void_p(d_pos), int(pos_is_f64),
+                                                 ctypes.c_void_p(d_energy),
+                                                 ctypes.c_void_p(d_forces) if d_forces else None))
+
+    def set_state(self, pos=None, vel=None):
+        p = self._pos(pos) if pos is not None else None
+        v = self._pos(vel) if vel is not None else None
+        self._check(self._lib.nnp_set_state(self._h, _dptr(p), _dptr(v)))
+
+    def get_state(self):
+        n, m = self.n_atoms, self.n_molecules
+        pos, vel, frc = (np.zeros((n, 3)) for _ in range(3))
+        pot, kin = np.zeros(m), np.zeros(m)
+        self._check(self._lib.nnp_get_state(self._h, _dptr(pos), _dptr(vel), _dptr(frc), _dptr(pot),
+                                            _dptr(kin)))
+        return {"pos": pos, "vel": vel, "forces": frc, "pot": pot, "kin": kin}
+
+    def step(self, dt: float, n_steps: int, graph: bool = True):
+        self._check(self._lib.nnp_step(self._h, float(dt), int(n_steps), 1 if graph else 0))
+
+    def energy_log(self, count: int):
+        m = self.n_molecules
+        U = np.zeros((count, m))
+        K = np.zeros((count, m))
+        w = ctypes.c_int32(0)
+        self._check(self._lib.nnp_energy_log(self._h, int(count), _dptr(U), _dptr(K), ctypes.byref(w)))
+        return U[:w.value], K[:w.value]
+
+    def stats(self):
+        s = (ctypes.c_int64 * 7)()
+        self._check(self._lib.nnp_stats(self._h, s))
+        return {"evaluations": s[0], "rebuilds": s[1], "forced_rebuilds": s[2], "steps": s[3],
+                "max_pairlist": s[4], "max_radial": s[5], "max_angular": s[6]}
+
+    def descriptors(self, pos):
+        p = self._pos(pos)
+        G = np.zeros((self.n_atoms, 384), np.float32)
+        self._check(self._lib.nnp_debug_descriptors(
+            self._h, _dptr(p), G.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return G
+
+    def atom_energies(self):
+        e = np.zeros(self.n_atoms)
+        self._check(self._lib.nnp_debug_atom_energies(self._h, _dptr(e)))
+        return e
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_int64(0)
+        self._check(self._lib.nnp_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def autotune(self, cache_path: Optional[str] = None):
+        self._check(self._lib.nnp_autotune(self._h, cache_path.encode() if cache_path else None))
+
+    def time_kernels(self, reps: int = 50):
+        """Average ms per launch of (evaluation kernels, gather kernel)."""
+        ms = np.zeros(2)
+        self._check(self._lib.nnp_time_kernels(self._h, int(reps), _dptr(ms)))
+        return float(ms[0]), float(ms[1])

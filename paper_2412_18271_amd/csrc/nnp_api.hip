@@ -1,0 +1,897 @@
+// nnp_api.hip -- host runtime behind the C ABI declared in include/nnp.h.
+//
+// The context owns the device buffers, the atom permutation between caller
+// order and the internal (element, molecule, Morton) order, the stream, and
+// the cache of captured HIP graphs for multi-step MD blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nnp.h"
+#include "nnp_internal.h"
+#include "nnp_launch.h"
+
+using namespace nnp;
+
+namespace {
+
+constexpr int kShapes[4][2] = {{kH1, kNumFeat}, {kH2, kH1}, {kH3, kH2}, {1, kH3}};
+constexpr size_t kBlobPerElement = (size_t)kH1 * kNumFeat + kH1 + (size_t)kH2 * kH1 + kH2 + (size_t)kH3 * kH2 + kH3 + kH3 + 1;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct nnp_context {
+    std::string err;
+    // configuration
+    int n = 0, nmol = 0, cap = 160, T = 16;
+    nnp_dtype dtype = NNP_MLP_FP32;
+    nnp_path path = NNP_PATH_FUSED;
+    int rebuild_every = 20;
+    double skin = 1.0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // caller data
+    std::vector<int> species;      // caller order
+    std::vector<double> masses;    // caller order
+    std::vector<int> mol_of;       // caller order
+    std::vector<int> mol_offsets;  // caller order
+    std::vector<float> weights;
+    // layout (valid once positions were given)
+    bool laid_out = false;
+    std::vector<int> perm;   // internal -> caller
+    std::vector<int> iperm;  // caller -> internal
+    // device
+    std::vector<DevBuf> bufs;
+    Sys S{};
+    bool forces_current = false;
+    bool kick_pending = false;  // previous block ended after a completed step (mode 1)
+    std::map<std::tuple<int, double, int, int, int>, hipGraphExec_t> graphs;
+    // pinned staging
+    double* h_stage = nullptr;
+    size_t h_stage_bytes = 0;
+};
+
+namespace {
+
+nnp_status fail(nnp_context* c, nnp_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+nnp_status hip_fail(nnp_context* c, hipError_t e, const char* where)
+{
+    return fail(c, e == hipErrorOutOfMemory ? NNP_ERR_OOM : NNP_ERR_HIP,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+void* dev_alloc(nnp_context* c, size_t bytes, hipError_t* e)
+{
+    void* p = nullptr;
+    *e = hipMalloc(&p, bytes < 256 ? 256 : bytes);
+    if (*e != hipSuccess) return nullptr;
+    *e = hipMemset(p, 0, bytes < 256 ? 256 : bytes);
+    if (*e != hipSuccess) {
+        (void)hipFree(p);
+        return nullptr;
+    }
+    c->bufs.push_back({p, bytes});
+    return p;
+}
+
+uint32_t spread_bits(uint32_t v)
+{
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000FF;
+    v = (v | (v << 8)) & 0x0300F00F;
+    v = (v | (v << 4)) & 0x030C30C3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
+// Validates host positions of every molecule: finite, and no two atoms of
+// one molecule closer than 1e-6 A (hash on a 1 A grid).
+nnp_status check_positions(nnp_context* c, const double* pos)
+{
+    for (int i = 0; i < 3 * c->n; ++i)
+        if (!std::isfinite(pos[i])) return fail(c, NNP_ERR_NONFINITE, "non-finite position component");
+    std::unordered_map<long long, std::vector<int>> grid;
+    for (int m = 0; m < c->nmol; ++m) {
+        grid.clear();
+        for (int i = c->mol_offsets[m]; i < c->mol_offsets[m + 1]; ++i) {
+            const long long gx = (long long)std::floor(pos[3 * i]), gy = (long long)std::floor(pos[3 * i + 1]),
+                            gz = (long long)std::floor(pos[3 * i + 2]);
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const long long key = ((gx + dx) * 73856093LL) ^ ((gy + dy) * 19349663LL) ^ ((gz + dz) * 83492791LL);
+                        auto it = grid.find(key);
+                        if (it == grid.end()) continue;
+                        for (int j : it->second) {
+                            const double ex = pos[3 * i] - pos[3 * j], ey = pos[3 * i + 1] - pos[3 * j + 1],
+                                         ez = pos[3 * i + 2] - pos[3 * j + 2];
+                            if (ex * ex + ey * ey + ez * ez < 1e-12) {
+                                char b[128];
+                                snprintf(b, sizeof b, "atoms %d and %d coincide", j, i);
+                                return fail(c, NNP_ERR_NONFINITE, b);
+                            }
+                        }
+                    }
+            const long long key = (gx * 73856093LL) ^ (gy * 19349663LL) ^ (gz * 83492791LL);
+            grid[key].push_back(i);
+        }
+    }
+    return NNP_OK;
+}
+
+// Builds the internal order from the first positions and uploads every
+// per-atom constant.
+nnp_status lay_out(nnp_context* c, const double* pos)
+{
+    const int n = c->n;
+    std::vector<uint64_t> key(n);
+    for (int m = 0; m < c->nmol; ++m) {
+        const int lo = c->mol_offsets[m], hi = c->mol_offsets[m + 1];
+        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        for (int i = lo; i < hi; ++i)
+            for (int d = 0; d < 3; ++d) {
+                mn[d] = std::min(mn[d], pos[3 * i + d]);
+                mx[d] = std::max(mx[d], pos[3 * i + d]);
+            }
+        for (int i = lo; i < hi; ++i) {
+            uint32_t q[3];
+            for (int d = 0; d < 3; ++d) {
+                const double span = std::max(mx[d] - mn[d], 1e-9);
+                q[d] = (uint32_t)std::min(1023.0, std::floor((pos[3 * i + d] - mn[d]) / span * 1023.999));
+            }
+            const uint64_t morton = spread_bits(q[0]) | (spread_bits(q[1]) << 1) | (spread_bits(q[2]) << 2);
+            key[i] = ((uint64_t)c->species[i] << 60) | ((uint64_t)m << 32) | morton;
+        }
+    }
+    c->perm.resize(n);
+    std::iota(c->perm.begin(), c->perm.end(), 0);
+    std::stable_sort(c->perm.begin(), c->perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    c->iperm.assign(n, 0);
+    for (int k = 0; k < n; ++k) c->iperm[c->perm[k]] = k;
+
+    // per-atom constants in internal order
+    std::vector<double4> p4(n);
+    std::vector<double> kinv(n), mass(n);
+    std::vector<int> mol(n);
+    for (int k = 0; k < n; ++k) {
+        const int i = c->perm[k];
+        p4[k] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], (double)c->species[i]);
+        mass[k] = c->masses[i];
+        kinv[k] = kKappa / c->masses[i];
+        mol[k] = c->mol_of[i];
+    }
+    // molecule x element ranges
+    std::vector<int2> mr((size_t)c->nmol * 4, make_int2(0, 0));
+    for (int k = 0; k < n;) {
+        const int m = mol[k], e = (int)p4[k].w;
+        int k2 = k;
+        while (k2 < n && mol[k2] == m && (int)p4[k2].w == e) ++k2;
+        mr[(size_t)m * 4 + e] = make_int2(k, k2);
+        k = k2;
+    }
+    // tiles: T consecutive atoms of one element
+    std::vector<int4> tiles;
+    for (int k = 0; k < n;) {
+        const int e = (int)p4[k].w;
+        int k2 = k;
+        while (k2 < n && (int)p4[k2].w == e && k2 - k < c->T) ++k2;
+        tiles.push_back(make_int4(k, k2 - k, e, 0));
+        k = k2;
+    }
+    std::vector<int> perm_dev(c->perm.begin(), c->perm.end());
+    Sys& S = c->S;
+    S.ntiles = (int)tiles.size();
+    HIP_TRY(c, hipMemcpy(S.pos, p4.data(), sizeof(double4) * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)S.kinv, kinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)S.mass, mass.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)S.mol, mol.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)S.mrange, mr.data(), sizeof(int2) * mr.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)S.perm, perm_dev.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    // the context stream does not synchronise with the null stream
+    HIP_TRY(c, hipDeviceSynchronize());
+    c->laid_out = true;
+    return NNP_OK;
+}
+
+// Rebuilds the tile table for a new atoms-per-tile value.
+nnp_status retile(nnp_context* c, int T)
+{
+    c->T = T;
+    if (!c->laid_out) return NNP_OK;
+    std::vector<int4> tiles;
+    const int n = c->n;
+    for (int k = 0; k < n;) {
+        const int e = c->species[c->perm[k]];
+        int k2 = k;
+        while (k2 < n && c->species[c->perm[k2]] == e && k2 - k < T) ++k2;
+        tiles.push_back(make_int4(k, k2 - k, e, 0));
+        k = k2;
+    }
+    c->S.ntiles = (int)tiles.size();
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy((void*)c->S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipDeviceSynchronize());
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    return NNP_OK;
+}
+
+void build_weights(const std::vector<float>& blob, std::vector<float>& w32, std::vector<uint16_t>& frag)
+{
+    w32.assign((size_t)4 * W32Layout::Stride, 0.f);
+    frag.assign((size_t)4 * 2 * FragLayout::Count * 64 * 8, 0);
+    auto bf16 = [](float x) -> uint16_t {  // round to nearest even
+        uint32_t u;
+        std::memcpy(&u, &x, 4);
+        if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    };
+    for (int e = 0; e < 4; ++e) {
+        const float* p = blob.data() + (size_t)e * kBlobPerElement;
+        const float* W[4];
+        const float* b[4];
+        size_t off = 0;
+        for (int l = 0; l < 4; ++l) {
+            W[l] = p + off;
+            off += (size_t)kShapes[l][0] * kShapes[l][1];
+            b[l] = p + off;
+            off += kShapes[l][0];
+        }
+        float* o = w32.data() + (size_t)e * W32Layout::Stride;
+        auto put_t = [&](int dst, const float* Wm, int M, int K) {  // [K][M] = W^T
+            for (int k = 0; k < K; ++k)
+                for (int m = 0; m < M; ++m) o[dst + k * M + m] = Wm[(size_t)m * K + k];
+        };
+        auto put = [&](int dst, const float* Wm, int M, int K) {
+            std::memcpy(o + dst, Wm, sizeof(float) * M * K);
+        };
+        put_t(W32Layout::Wt1, W[0], kH1, kNumFeat);
+        put(W32Layout::W1, W[0], kH1, kNumFeat);
+        put_t(W32Layout::Wt2, W[1], kH2, kH1);
+        put(W32Layout::W2, W[1], kH2, kH1);
+        put_t(W32Layout::Wt3, W[2], kH3, kH2);
+        put(W32Layout::W3, W[2], kH3, kH2);
+        std::memcpy(o + W32Layout::W4, W[3], sizeof(float) * kH3);
+        std::memcpy(o + W32Layout::B1, b[0], sizeof(float) * kH1);
+        std::memcpy(o + W32Layout::B2, b[1], sizeof(float) * kH2);
+        std::memcpy(o + W32Layout::B3, b[2], sizeof(float) * kH3);
+        o[W32Layout::B4] = b[3][0];
+        // MFMA A fragments: fragment (mt, kt), lane l, value i holds
+        // A[16 mt + l % 16][32 kt + 8 (l / 16) + i]
+        // hi fragments, then lo = bf16(w - hi) fragments of the same layout
+        uint16_t* fr = frag.data() + (size_t)e * 2 * FragLayout::Count * 512;
+        uint16_t* frl = fr + (size_t)FragLayout::Count * 512;
+        auto put_frag = [&](int base, int M, int K, bool transpose, const float* Wm, int ldw) {
+            const int KT = K / 32;
+            for (int mt = 0; mt < M / 16; ++mt)
+                for (int kt = 0; kt < KT; ++kt)
+                    for (int l = 0; l < 64; ++l)
+                        for (int i = 0; i < 8; ++i) {
+                            const int r = 16 * mt + (l % 16), k = 32 * kt + 8 * (l / 16) + i;
+                            const float v = transpose ? Wm[(size_t)k * ldw + r] : Wm[(size_t)r * ldw + k];
+                            const size_t at = ((size_t)(base + mt * KT + kt) * 64 + l) * 8 + i;
+                            const uint16_t h = bf16(v);
+                            uint32_t hb = (uint32_t)h << 16;
+                            float hf;
+                            std::memcpy(&hf, &hb, 4);
+                            fr[at] = h;
+                            frl[at] = bf16(v - hf);
+                        }
+        };
+        put_frag(FragLayout::F1, kH1, kNumFeat, false, W[0], kNumFeat);
+        put_frag(FragLayout::F2, kH2, kH1, false, W[1], kH1);
+        put_frag(FragLayout::F3, kH3, kH2, false, W[2], kH2);
+        put_frag(FragLayout::B3, kH2, kH3, true, W[2], kH2);
+        put_frag(FragLayout::B2, kH1, kH2, true, W[1], kH1);
+        put_frag(FragLayout::B1, kNumFeat, kH1, true, W[0], kNumFeat);
+    }
+}
+
+int mode_of(const nnp_context* c)
+{
+    return c->dtype == NNP_MLP_BF16 ? 1 : c->dtype == NNP_MLP_BF16_SPLIT ? 2 : 0;
+}
+
+hipError_t enqueue_eval(nnp_context* c, bool grad)
+{
+    return launch_eval(c->S, c->path == NNP_PATH_FUSED ? 1 : 0, mode_of(c), c->T, grad, c->stream);
+}
+
+// Evaluation at the current positions without integration (forces, energies).
+hipError_t enqueue_compute(nnp_context* c, bool grad)
+{
+    hipError_t e = enqueue_eval(c, grad);
+    if (e != hipSuccess) return e;
+    if (!grad) {
+        // energy-only: per-slot forces are not written; the gather would read
+        // stale slots, so zero-force semantics are not provided -- only the
+        // energies of this evaluation are meaningful
+    }
+    return launch_gather_integrate(c->S, 0.0, 0, c->stream);
+}
+
+hipError_t enqueue_steps(nnp_context* c, double dt, int nsteps, bool first_kick)
+{
+    hipError_t e = hipSuccess;
+    if (first_kick) e = launch_kickdrift(c->S, dt, c->stream);
+    for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
+        e = enqueue_eval(c, true);
+        if (e == hipSuccess) e = launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream);
+    }
+    return e;
+}
+
+nnp_status check_device_flags(nnp_context* c)
+{
+    StepState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->S.st, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (st.overflow) {
+        char b[256];
+        snprintf(b, sizeof b,
+                 "capacity exceeded: largest pair list %d (max_neighbors %d), neighbours within 5.2 A %d (max %d), "
+                 "within 3.5 A %d (max %d)",
+                 st.max_ns, c->cap, st.max_nr, kRadMax, st.max_na, kAngMax);
+        return fail(c, NNP_ERR_STATE, b);
+    }
+    if (st.nonfinite) return fail(c, NNP_ERR_NONFINITE, "non-finite energy or force on the device");
+    return NNP_OK;
+}
+
+nnp_status upload_positions(nnp_context* c, const double* pos)
+{
+    nnp_status s = check_positions(c, pos);
+    if (s != NNP_OK) return s;
+    if (!c->laid_out) return lay_out(c, pos);
+    HIP_TRY(c, hipMemcpyAsync(c->S.stage, pos, sizeof(double) * 3 * c->n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_positions_in(c->S, c->S.stage, 1, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NNP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nnp_status_string(nnp_status s)
+{
+    switch (s) {
+        case NNP_OK: return "NNP_OK";
+        case NNP_ERR_ARG: return "NNP_ERR_ARG";
+        case NNP_ERR_NONFINITE: return "NNP_ERR_NONFINITE";
+        case NNP_ERR_UNSUPPORTED: return "NNP_ERR_UNSUPPORTED";
+        case NNP_ERR_OOM: return "NNP_ERR_OOM";
+        case NNP_ERR_HIP: return "NNP_ERR_HIP";
+        case NNP_ERR_STATE: return "NNP_ERR_STATE";
+    }
+    return "NNP_ERR_UNKNOWN";
+}
+
+const char* nnp_last_error(const nnp_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static nnp_status validate_params(const nnp_params* p, std::string& msg)
+{
+    if (!p) return msg = "params is NULL", NNP_ERR_ARG;
+    if (p->n_atoms <= 0) return msg = "n_atoms must be > 0", NNP_ERR_ARG;
+    if (p->n_molecules < 1 || p->n_molecules > p->n_atoms) return msg = "n_molecules out of range", NNP_ERR_ARG;
+    if (p->n_molecules > 1 && !p->mol_offsets) return msg = "mol_offsets is NULL", NNP_ERR_ARG;
+    if (p->mol_offsets) {
+        if (p->mol_offsets[0] != 0 || p->mol_offsets[p->n_molecules] != p->n_atoms)
+            return msg = "mol_offsets must start at 0 and end at n_atoms", NNP_ERR_ARG;
+        for (int m = 0; m < p->n_molecules; ++m)
+            if (p->mol_offsets[m + 1] <= p->mol_offsets[m]) return msg = "empty or decreasing molecule", NNP_ERR_ARG;
+    }
+    if (!p->species || !p->masses || !p->weights) return msg = "species, masses and weights are required", NNP_ERR_ARG;
+    for (int i = 0; i < p->n_atoms; ++i) {
+        if (p->species[i] < 0 || p->species[i] > 3) return msg = "species outside {0,1,2,3}", NNP_ERR_ARG;
+        if (!(p->masses[i] > 0.0) || !std::isfinite(p->masses[i])) return msg = "mass must be finite and > 0", NNP_ERR_ARG;
+    }
+    if (p->weights_count != 4 * kBlobPerElement) return msg = "weights_count must be 4 * 94689", NNP_ERR_ARG;
+    for (size_t i = 0; i < p->weights_count; ++i)
+        if (!std::isfinite(p->weights[i])) return msg = "non-finite weight", NNP_ERR_NONFINITE;
+    if (p->mlp_dtype == NNP_MLP_FP8) return msg = "FP8 network GEMMs are not available", NNP_ERR_UNSUPPORTED;
+    if (p->mlp_dtype != NNP_MLP_FP32 && p->mlp_dtype != NNP_MLP_BF16 && p->mlp_dtype != NNP_MLP_BF16_SPLIT)
+        return msg = "unknown mlp_dtype", NNP_ERR_ARG;
+    if (p->path != NNP_PATH_PLAIN && p->path != NNP_PATH_FUSED) return msg = "unknown path", NNP_ERR_ARG;
+    if (p->rebuild_every < 1) return msg = "rebuild_every must be >= 1", NNP_ERR_ARG;
+    if (!(p->skin >= 0.0) || !std::isfinite(p->skin) || p->skin > 5.0) return msg = "skin must be in [0, 5] A", NNP_ERR_ARG;
+    if (p->max_neighbors < 0 || p->max_neighbors > kCapMax) return msg = "max_neighbors must be in [0, 256]", NNP_ERR_ARG;
+    if (p->path == NNP_PATH_FUSED && p->atoms_per_tile != 0 && p->atoms_per_tile != 4 && p->atoms_per_tile != 8)
+        return msg = "atoms_per_tile of the fused path must be 0, 4 or 8", NNP_ERR_ARG;
+    if (p->path == NNP_PATH_PLAIN && p->atoms_per_tile != 0 && p->atoms_per_tile != 8 && p->atoms_per_tile != 16)
+        return msg = "atoms_per_tile of the plain path must be 0, 8 or 16", NNP_ERR_ARG;
+    return NNP_OK;
+}
+
+nnp_status nnp_create(const nnp_params* p, nnp_context** out)
+{
+    if (!out) return NNP_ERR_ARG;
+    *out = nullptr;
+    std::string msg;
+    nnp_status s = validate_params(p, msg);
+    if (s != NNP_OK) {
+        fprintf(stderr, "nnp_create: %s\n", msg.c_str());
+        return s;
+    }
+    nnp_context* c = new (std::nothrow) nnp_context();
+    if (!c) return NNP_ERR_OOM;
+    c->n = p->n_atoms;
+    c->nmol = p->n_molecules;
+    c->cap = p->max_neighbors ? p->max_neighbors : 192;
+    c->T = p->atoms_per_tile ? p->atoms_per_tile : (p->path == NNP_PATH_FUSED ? 8 : 16);
+    c->dtype = p->mlp_dtype;
+    c->path = p->path;
+    c->rebuild_every = p->rebuild_every;
+    c->skin = p->skin;
+    c->species.assign(p->species, p->species + c->n);
+    c->masses.assign(p->masses, p->masses + c->n);
+    c->weights.assign(p->weights, p->weights + p->weights_count);
+    if (p->mol_offsets)
+        c->mol_offsets.assign(p->mol_offsets, p->mol_offsets + c->nmol + 1);
+    else
+        c->mol_offsets = {0, c->n};
+    c->mol_of.assign(c->n, 0);
+    for (int m = 0; m < c->nmol; ++m)
+        for (int i = c->mol_offsets[m]; i < c->mol_offsets[m + 1]; ++i) c->mol_of[i] = m;
+
+    hipError_t e = hipSuccess;
+    if (p->stream) {
+        c->stream = (hipStream_t)p->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            nnp_status r = hip_fail(c, e, "hipStreamCreate");
+            fprintf(stderr, "nnp_create: %s\n", c->err.c_str());
+            delete c;
+            return r;
+        }
+        c->own_stream = true;
+    }
+    const size_t n = c->n, cap = c->cap, nm = c->nmol;
+    Sys& S = c->S;
+    S.n = c->n;
+    S.nmol = c->nmol;
+    S.cap = c->cap;
+    S.rebuild_every = c->rebuild_every;
+    S.rlist2 = (float)((5.2 + c->skin) * (5.2 + c->skin));
+    S.half_skin2 = (float)(0.25 * c->skin * c->skin);
+#define ALLOC(field, type, count)                                         \
+    S.field = (type)dev_alloc(c, sizeof(*S.field) * (size_t)(count), &e); \
+    if (e != hipSuccess) goto oom;
+    ALLOC(pos, double4*, n)
+    ALLOC(vel, double4*, n)
+    ALLOC(frc, double4*, n)
+    ALLOC(ref, float4*, n)
+    ALLOC(kinv, const double*, n)
+    ALLOC(mass, const double*, n)
+    ALLOC(mol, const int*, n)
+    ALLOC(mrange, const int2*, nm * 4)
+    ALLOC(tiles, const int4*, n)
+    ALLOC(nbr, int*, n * cap)
+    ALLOC(ncnt, int*, n)
+    ALLOC(rev, int*, n * cap)
+    ALLOC(fslot, float4*, n * cap)
+    ALLOC(Ei, float*, n)
+    ALLOC(Uring, double*, (size_t)kRing * nm)
+    ALLOC(Kring, double*, (size_t)kRing * nm)
+    ALLOC(Eacc, double*, nm)
+    ALLOC(Kacc, double*, nm)
+    ALLOC(Ecur, double*, nm)
+    ALLOC(Kcur, double*, nm)
+    ALLOC(perm, const int*, n)
+    ALLOC(stage, double*, 3 * n)
+    ALLOC(st, StepState*, 1)
+    ALLOC(w32, const float*, (size_t)4 * W32Layout::Stride)
+    S.wfrag = dev_alloc(c, (size_t)4 * 2 * FragLayout::Count * 1024, &e);
+    if (e != hipSuccess) goto oom;
+    if (c->path == NNP_PATH_PLAIN) {
+        ALLOC(G, float*, n * kNumFeat)
+        ALLOC(dG, float*, n * kNumFeat)
+    }
+#undef ALLOC
+    {
+        std::vector<float> w32;
+        std::vector<uint16_t> frag;
+        build_weights(c->weights, w32, frag);
+        e = hipMemcpy((void*)S.w32, w32.data(), sizeof(float) * w32.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void*)S.wfrag, frag.data(), sizeof(uint16_t) * frag.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) goto oom;
+    }
+    *out = c;
+    return NNP_OK;
+oom:
+    {
+        nnp_status r = hip_fail(c, e, "device allocation");
+        fprintf(stderr, "nnp_create: %s\n", c->err.c_str());
+        nnp_destroy(c);
+        return r;
+    }
+}
+
+void nnp_destroy(nnp_context* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& b : c->bufs) (void)hipFree(b.p);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+nnp_status nnp_set_state(nnp_context* c, const double* pos, const double* vel)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (vel)
+        for (int i = 0; i < 3 * c->n; ++i)
+            if (!std::isfinite(vel[i])) return fail(c, NNP_ERR_NONFINITE, "non-finite velocity component");
+    if (pos) {
+        nnp_status s = upload_positions(c, pos);
+        if (s != NNP_OK) return s;
+        hipError_t e = launch_invalidate_lists(c->S, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "invalidate");
+        c->forces_current = false;
+        c->kick_pending = false;
+    }
+    if (vel) {
+        if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before velocities");
+        std::vector<double4> v4(c->n);
+        for (int k = 0; k < c->n; ++k) {
+            const int i = c->perm[k];
+            v4[k] = make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.0);
+        }
+        HIP_TRY(c, hipMemcpyAsync(c->S.vel, v4.data(), sizeof(double4) * c->n, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (c->kick_pending) c->forces_current = true;  // forces unchanged, velocities replaced
+    }
+    c->err.clear();
+    return NNP_OK;
+}
+
+nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, double* energy, double* forces)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (box) return fail(c, NNP_ERR_UNSUPPORTED, "periodic boxes are not supported (gas phase only)");
+    if (!pos || !energy) return fail(c, NNP_ERR_ARG, "pos and energy are required");
+    nnp_status s = upload_positions(c, pos);
+    if (s != NNP_OK) return s;
+    HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
+    HIP_TRY(c, enqueue_compute(c, true));
+    std::vector<double4> f4;
+    if (forces) {
+        f4.resize(c->n);
+        HIP_TRY(c, hipMemcpyAsync(f4.data(), c->S.frc, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(energy, c->S.Ecur, sizeof(double) * c->nmol, hipMemcpyDeviceToHost, c->stream));
+    s = check_device_flags(c);
+    if (s != NNP_OK) return s;
+    if (forces)
+        for (int k = 0; k < c->n; ++k) {
+            const int i = c->perm[k];
+            forces[3 * i] = f4[k].x;
+            forces[3 * i + 1] = f4[k].y;
+            forces[3 * i + 2] = f4[k].z;
+        }
+    c->forces_current = true;
+    c->kick_pending = false;
+    c->err.clear();
+    return NNP_OK;
+}
+
+nnp_status nnp_compute_device(nnp_context* c, const void* d_pos, int is_f64, double* d_energy, double* d_forces)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!d_pos || !d_energy) return fail(c, NNP_ERR_ARG, "d_pos and d_energy are required");
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions once with nnp_set_state or nnp_compute first");
+    HIP_TRY(c, launch_positions_in(c->S, d_pos, is_f64 ? 1 : 0, c->stream));
+    HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
+    const bool grad = d_forces != nullptr;
+    HIP_TRY(c, enqueue_eval(c, grad));
+    if (grad) {
+        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+        HIP_TRY(c, launch_forces_out(c->S, d_forces, c->stream));
+    } else {
+        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+    }
+    HIP_TRY(c, launch_energy_out(c->S, d_energy, c->stream));
+    c->forces_current = grad;
+    c->kick_pending = false;
+    return NNP_OK;
+}
+
+nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, NNP_ERR_ARG, "dt must be finite and > 0");
+    if (nsteps < 0) return fail(c, NNP_ERR_ARG, "n_steps must be >= 0");
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before stepping");
+    if (nsteps == 0) return NNP_OK;
+    if (!c->forces_current) {
+        HIP_TRY(c, enqueue_compute(c, true));
+        c->forces_current = true;
+    }
+    if (!use_graph) {
+        HIP_TRY(c, enqueue_steps(c, dt, nsteps, true));
+        c->kick_pending = true;
+        return NNP_OK;
+    }
+    const int B = std::min<int>(nsteps, 100);
+    auto run_block = [&](int len) -> nnp_status {
+        const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            hipGraph_t g;
+            HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_steps(c, dt, len, true);
+            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            if (e != hipSuccess) return hip_fail(c, e, "capture");
+            if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+            hipGraphExec_t x;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+            it = c->graphs.emplace(key, x).first;
+        }
+        HIP_TRY(c, hipGraphLaunch(it->second, c->stream));
+        return NNP_OK;
+    };
+    int left = nsteps;
+    while (left > 0) {
+        const int len = left >= B ? B : left;
+        nnp_status s = run_block(len);
+        if (s != NNP_OK) return s;
+        left -= len;
+    }
+    c->kick_pending = true;
+    return NNP_OK;
+}
+
+nnp_status nnp_get_state(nnp_context* c, double* pos, double* vel, double* forces, double* pot, double* kin)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "no positions set");
+    std::vector<double4> p4, v4, f4;
+    if (pos) {
+        p4.resize(c->n);
+        HIP_TRY(c, hipMemcpyAsync(p4.data(), c->S.pos, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (vel) {
+        v4.resize(c->n);
+        HIP_TRY(c, hipMemcpyAsync(v4.data(), c->S.vel, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (forces) {
+        f4.resize(c->n);
+        HIP_TRY(c, hipMemcpyAsync(f4.data(), c->S.frc, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (pot) HIP_TRY(c, hipMemcpyAsync(pot, c->S.Ecur, sizeof(double) * c->nmol, hipMemcpyDeviceToHost, c->stream));
+    if (kin) HIP_TRY(c, hipMemcpyAsync(kin, c->S.Kcur, sizeof(double) * c->nmol, hipMemcpyDeviceToHost, c->stream));
+    nnp_status s = check_device_flags(c);
+    if (s != NNP_OK) return s;
+    for (int k = 0; k < c->n; ++k) {
+        const int i = c->perm[k];
+        if (pos) {
+            pos[3 * i] = p4[k].x;
+            pos[3 * i + 1] = p4[k].y;
+            pos[3 * i + 2] = p4[k].z;
+        }
+        if (vel) {
+            vel[3 * i] = v4[k].x;
+            vel[3 * i + 1] = v4[k].y;
+            vel[3 * i + 2] = v4[k].z;
+        }
+        if (forces) {
+            forces[3 * i] = f4[k].x;
+            forces[3 * i + 1] = f4[k].y;
+            forces[3 * i + 2] = f4[k].z;
+        }
+    }
+    return NNP_OK;
+}
+
+nnp_status nnp_energy_log(nnp_context* c, int32_t count, double* U, double* K, int32_t* written)
+{
+    if (!c || !U || !K || !written || count < 0) return fail(c, NNP_ERR_ARG, "bad arguments");
+    StepState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->S.st, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // the most recent evaluation sits in last_slot; evaluations of steps are
+    // consecutive slots
+    const int have = st.n_eval > 0 ? std::min(st.last_slot + 1, kRing) : 0;
+    const int w = std::min(count, have);
+    const size_t nm = c->nmol;
+    std::vector<double> u(nm), k(nm);
+    for (int q = 0; q < w; ++q) {
+        const int slot = ((st.last_slot - (w - 1 - q)) % kRing + kRing) % kRing;
+        HIP_TRY(c, hipMemcpy(U + (size_t)q * nm, c->S.Uring + (size_t)slot * nm, sizeof(double) * nm, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(K + (size_t)q * nm, c->S.Kring + (size_t)slot * nm, sizeof(double) * nm, hipMemcpyDeviceToHost));
+    }
+    *written = w;
+    return NNP_OK;
+}
+
+nnp_status nnp_stats(nnp_context* c, int64_t* stats)
+{
+    if (!c || !stats) return fail(c, NNP_ERR_ARG, "bad arguments");
+    StepState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->S.st, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    stats[0] = st.n_eval;
+    stats[1] = st.n_rebuild;
+    stats[2] = st.n_forced;
+    stats[3] = st.step;
+    stats[4] = st.max_ns;
+    stats[5] = st.max_nr;
+    stats[6] = st.max_na;
+    return NNP_OK;
+}
+
+nnp_status nnp_debug_descriptors(nnp_context* c, const double* pos, float* G)
+{
+    if (!c || !pos || !G) return fail(c, NNP_ERR_ARG, "bad arguments");
+    nnp_status s = upload_positions(c, pos);
+    if (s != NNP_OK) return s;
+    Sys S = c->S;
+    float* dG = nullptr;
+    if (!S.G) {
+        HIP_TRY(c, hipMalloc(&dG, sizeof(float) * (size_t)c->n * kNumFeat));
+        S.G = dG;
+    }
+    hipError_t e = launch_invalidate_lists(S, c->stream);
+    if (e == hipSuccess) e = launch_descriptors_only(S, c->stream);
+    std::vector<float> tmp((size_t)c->n * kNumFeat);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tmp.data(), S.G, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (dG) (void)hipFree(dG);
+    if (e != hipSuccess) return hip_fail(c, e, "descriptors");
+    s = check_device_flags(c);
+    if (s != NNP_OK) return s;
+    for (int k = 0; k < c->n; ++k)
+        std::memcpy(G + (size_t)c->perm[k] * kNumFeat, tmp.data() + (size_t)k * kNumFeat, sizeof(float) * kNumFeat);
+    // the lists were built outside a step; the next evaluation rebuilds them
+    HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
+    c->forces_current = false;
+    c->kick_pending = false;
+    return NNP_OK;
+}
+
+nnp_status nnp_debug_atom_energies(nnp_context* c, double* Ei)
+{
+    if (!c || !Ei) return fail(c, NNP_ERR_ARG, "bad arguments");
+    std::vector<float> e(c->n);
+    HIP_TRY(c, hipMemcpyAsync(e.data(), c->S.Ei, sizeof(float) * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n; ++k) Ei[c->perm[k]] = e[k];
+    return NNP_OK;
+}
+
+nnp_status nnp_device_bytes(nnp_context* c, int64_t* bytes)
+{
+    if (!c || !bytes) return fail(c, NNP_ERR_ARG, "bad arguments");
+    int64_t b = 0;
+    for (auto& x : c->bufs) b += (int64_t)x.bytes;
+    *bytes = b;
+    return NNP_OK;
+}
+
+nnp_status nnp_time_kernels(nnp_context* c, int32_t reps, double* ms)
+{
+    if (!c || !ms || reps < 1) return fail(c, NNP_ERR_ARG, "bad arguments");
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions first");
+    HIP_TRY(c, enqueue_compute(c, true));
+    hipEvent_t e0, e1, e2;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventCreate(&e2));
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) HIP_TRY(c, enqueue_eval(c, true));
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    for (int r = 0; r < reps; ++r) HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+    HIP_TRY(c, hipEventRecord(e2, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e2));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&a, e0, e1));
+    HIP_TRY(c, hipEventElapsedTime(&b, e1, e2));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    ms[0] = a / reps;
+    ms[1] = b / reps;
+    c->forces_current = true;
+    c->kick_pending = false;
+    return check_device_flags(c);
+}
+
+nnp_status nnp_autotune(nnp_context* c, const char* cache_path)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before autotuning");
+    const std::string key = "n" + std::to_string(c->n) + "_m" + std::to_string(c->nmol) + "_p" +
+                            std::to_string((int)c->path) + "_d" + std::to_string((int)c->dtype);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const std::string pat = "\"key\": \"" + key + "\"";
+            if (line.find(pat) == std::string::npos) continue;
+            const size_t p = line.find("\"atoms_per_tile\": ");
+            if (p == std::string::npos) continue;
+            const int T = std::atoi(line.c_str() + p + 18);
+            if (T == 4 || T == 8 || T == 16) return retile(c, T);
+        }
+    }
+    const int cand[2] = {c->path == NNP_PATH_FUSED ? 4 : 8, c->path == NNP_PATH_FUSED ? 8 : 16};
+    double best = 1e300;
+    int bestT = c->T;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    std::ostringstream times;
+    for (int T : cand) {
+        nnp_status s = retile(c, T);
+        if (s != NNP_OK) return s;
+        HIP_TRY(c, enqueue_eval(c, true));  // warm-up (also builds the lists)
+        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        const int reps = 20;
+        for (int r = 0; r < reps; ++r) {
+            HIP_TRY(c, enqueue_eval(c, true));
+            HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+        }
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        times << (times.tellp() > 0 ? ", " : "") << "\"" << T << "\": " << ms / reps;
+        if (ms < best) {
+            best = ms;
+            bestT = T;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    nnp_status s = retile(c, bestT);
+    if (s != NNP_OK) return s;
+    nnp_status f = check_device_flags(c);
+    if (f != NNP_OK) return f;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << "{\"key\": \"" << key << "\", \"atoms_per_tile\": " << bestT << ", \"ms_per_eval\": {" << times.str()
+          << "}}\n";
+    }
+    return NNP_OK;
+}
+
+}  // extern "C"

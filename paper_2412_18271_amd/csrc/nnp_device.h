@@ -1,0 +1,675 @@
+// nnp_device.h -- wave-level device functions of one energy/force evaluation.
+//
+// One wavefront (64 lanes) owns one centre atom for the pair-list build, the
+// environment load, the descriptors and the adjoint.  The network stage is a
+// workgroup-wide operation over a tile of atoms of one element.
+//
+// Model (the symmetry-function network potential behind the paper's
+// force-provider contract, Methods section):
+//   radial   G[16 s_j + k]       = sum_j exp(-16 (r_ij - R_k)^2) fc(r_ij; 5.2),  R_k = 0.9 + 0.28 k
+//   angular  G[64 + 32 p + 8m + n] = sum_{j<k} 2^-31 (1 + c' cos t_n + sqrt(1-c'^2) sin t_n)^32
+//                                  * exp(-8 ((r_ij + r_ik)/2 - Q_m)^2) fc(r_ij; 3.5) fc(r_ik; 3.5),
+//            c' = 0.95 cos(theta_jik), t_n = (2n+1) pi/16, Q_m = 0.9 + 0.65 m
+//   network  384 -> 160 -> 128 -> 96 -> 1, CELU(0.1); E = sum_i E_i; F = -dE/dx.
+#pragma once
+
+#include <type_traits>
+
+#include "nnp_internal.h"
+
+namespace nnp {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+__constant__ static const float kSecCos[8] = {9.807852507e-01f, 8.314695954e-01f, 5.555702448e-01f,
+                                               1.950903237e-01f, -1.950903237e-01f, -5.555702448e-01f,
+                                               -8.314695954e-01f, -9.807852507e-01f};
+__constant__ static const float kSecSin[8] = {1.950903237e-01f, 5.555702448e-01f, 8.314695954e-01f,
+                                               9.807852507e-01f, 9.807852507e-01f, 8.314695954e-01f,
+                                               5.555702448e-01f, 1.950903237e-01f};
+constexpr float kTwoPowM31 = 4.656612873e-10f;  // 2^(1 - zeta), zeta = 32
+constexpr float kPi = 3.14159265358979f;
+
+// Environment of one centre atom, in LDS.  Entries are the neighbours within
+// 5.2 A in ascending internal index (hence grouped by element).
+struct Env {
+    float4 geo[kRadMax];            // unit vector to the neighbour, distance
+    float2 fcr[kRadMax];            // fc(r; 5.2), dfc/dr
+    float2 afc[kAngMax];            // fc(r; 3.5), dfc/dr of angular entries
+    unsigned short info[kRadMax];   // element | (slot in the pair list) << 2
+    unsigned char ang[kAngMax];     // radial-entry index of neighbours within 3.5 A
+    unsigned char smap[kCapMax];    // pair-list slot -> radial entry, or 255
+    int nR, nA, nS;                 // radial entries, angular entries, pair-list length
+};
+constexpr unsigned char kNoEntry = 255;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Orders LDS accesses of the lanes of one wavefront: without it the compiler
+// may move a lane's read of a value another lane wrote above that write.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+}
+
+// Adds neighbour candidate to the wave's environment (called for every
+// accepted pair-list slot, in slot order, by all 64 lanes together).
+__device__ __forceinline__ void env_append(Env& E, bool valid, int slot, double dx, double dy, double dz,
+                                           int elem, int& nR, int& nA, int& over)
+{
+    float r = 0.0f;
+    bool inR = false, inA = false;
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+        double rd = sqrt(dx * dx + dy * dy + dz * dz);
+        r = (float)rd;
+        inR = r < kCutRad;
+        inA = r < kCutAng;
+        double inv = 1.0 / rd;
+        g = make_float4((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), r);
+    }
+    unsigned long long mR = __ballot(inR), mA = __ballot(inA);
+    int iR = nR + lanes_below(mR);
+    int iA = nA + lanes_below(mA);
+    if (valid) E.smap[slot] = (inR && iR < kRadMax) ? (unsigned char)iR : kNoEntry;
+    if (inR && iR < kRadMax) {
+        E.geo[iR] = g;
+        float x = r * (1.0f / kCutRad);
+        E.fcr[iR] = make_float2(0.5f * cospif(x) + 0.5f, -0.5f * (kPi / kCutRad) * sinpif(x));
+        E.info[iR] = (unsigned short)(elem | (slot << 2));
+        if (inA && iA < kAngMax) {
+            float y = r * (1.0f / kCutAng);
+            E.ang[iA] = (unsigned char)iR;
+            E.afc[iA] = make_float2(0.5f * cospif(y) + 0.5f, -0.5f * (kPi / kCutAng) * sinpif(y));
+        }
+    }
+    nR += __popcll(mR);
+    nA += __popcll(mA);
+    over |= (nR > kRadMax) | (nA > kAngMax);
+}
+
+__device__ __forceinline__ void env_finish(const Sys& S, Env& E, int nR, int nA, int nS, int over)
+{
+    if (lane_id() == 0) {
+        E.nR = nR < kRadMax ? nR : kRadMax;
+        E.nA = nA < kAngMax ? nA : kAngMax;
+        E.nS = nS;
+        if (over) atomicOr(&S.st->overflow, 1);
+        atomicMax(&S.st->max_ns, nS);
+        atomicMax(&S.st->max_nr, nR);
+        atomicMax(&S.st->max_na, nA);
+    }
+    wave_sync();
+}
+
+// Rebuilds the pair list of atom a (all atoms of its molecule closer than
+// 5.2 + skin, ascending index) and fills its environment from the scan.
+__device__ void build_list_env(const Sys& S, int a, Env& E)
+{
+    const int lane = lane_id();
+    const double4 pa = S.pos[a];
+    const int m = S.mol[a];
+    int count = 0, nR = 0, nA = 0, over = 0;
+    const size_t base = (size_t)a * S.cap;
+    for (int e = 0; e < kNumSpecies; ++e) {
+        const int2 rg = S.mrange[m * kNumSpecies + e];
+        for (int c0 = rg.x; c0 < rg.y; c0 += 64) {
+            const int c = c0 + lane;
+            bool ok = false;
+            double dx = 0, dy = 0, dz = 0;
+            if (c < rg.y && c != a) {
+                const double4 pc = S.pos[c];
+                dx = pc.x - pa.x;
+                dy = pc.y - pa.y;
+                dz = pc.z - pa.z;
+                ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
+            }
+            const unsigned long long mk = __ballot(ok);
+            const int slot = count + lanes_below(mk);
+            const bool keep = ok && slot < S.cap;
+            if (keep) S.nbr[base + slot] = c;
+            env_append(E, keep, slot, dx, dy, dz, e, nR, nA, over);
+            count += __popcll(mk);
+        }
+    }
+    over |= count > S.cap;
+    const int nS = count < S.cap ? count : S.cap;
+    if (lane == 0) {
+        S.ncnt[a] = nS;
+        S.ref[a] = make_float4((float)pa.x, (float)pa.y, (float)pa.z, 0.f);
+    }
+    env_finish(S, E, nR, nA, nS, over);
+}
+
+// Builds only the pair list (plain path).
+__device__ void build_list(const Sys& S, int a)
+{
+    const int lane = lane_id();
+    const double4 pa = S.pos[a];
+    const int m = S.mol[a];
+    int count = 0;
+    const size_t base = (size_t)a * S.cap;
+    for (int e = 0; e < kNumSpecies; ++e) {
+        const int2 rg = S.mrange[m * kNumSpecies + e];
+        for (int c0 = rg.x; c0 < rg.y; c0 += 64) {
+            const int c = c0 + lane;
+            bool ok = false;
+            if (c < rg.y && c != a) {
+                const double4 pc = S.pos[c];
+                const double dx = pc.x - pa.x, dy = pc.y - pa.y, dz = pc.z - pa.z;
+                ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
+            }
+            const unsigned long long mk = __ballot(ok);
+            const int slot = count + lanes_below(mk);
+            if (ok && slot < S.cap) S.nbr[base + slot] = c;
+            count += __popcll(mk);
+        }
+    }
+    if (lane == 0) {
+        S.ncnt[a] = count < S.cap ? count : S.cap;
+        S.ref[a] = make_float4((float)pa.x, (float)pa.y, (float)pa.z, 0.f);
+        if (count > S.cap) atomicOr(&S.st->overflow, 1);
+    }
+}
+
+// Loads the environment of atom a from its existing pair list.
+__device__ void load_env(const Sys& S, int a, Env& E)
+{
+    const int lane = lane_id();
+    const double4 pa = S.pos[a];
+    const int nS = S.ncnt[a];
+    const size_t base = (size_t)a * S.cap;
+    int nR = 0, nA = 0, over = 0;
+    for (int s0 = 0; s0 < nS; s0 += 64) {
+        const int s = s0 + lane;
+        const bool valid = s < nS;
+        double dx = 0, dy = 0, dz = 0;
+        int elem = 0;
+        if (valid) {
+            const double4 pj = S.pos[S.nbr[base + s]];
+            dx = pj.x - pa.x;
+            dy = pj.y - pa.y;
+            dz = pj.z - pa.z;
+            elem = (int)pj.w;
+        }
+        env_append(E, valid, s, dx, dy, dz, elem, nR, nA, over);
+    }
+    env_finish(S, E, nR, nA, nS, over);
+}
+
+// Radial features G[0..63] of the wave's atom.  Lane (k, q): Gaussian k,
+// neighbour subset q of 4; per-element sums, then a reduction over q.
+__device__ void radial_features(const Env& E, float* G)
+{
+    const int lane = lane_id();
+    const int k = lane & 15, q = lane >> 4;
+    const float Rk = 0.9f + 0.28f * (float)k;
+    const int nR = E.nR;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int e = q; e < nR; e += 4) {
+        const float r = E.geo[e].w;
+        const float x = r - Rk;
+        const float v = __expf(-kEtaRad * x * x) * E.fcr[e].x;
+        const int s = E.info[e] & 3;
+        a0 += s == 0 ? v : 0.f;
+        a1 += s == 1 ? v : 0.f;
+        a2 += s == 2 ? v : 0.f;
+        a3 += s == 3 ? v : 0.f;
+    }
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+        a0 += __shfl_xor(a0, off);
+        a1 += __shfl_xor(a1, off);
+        a2 += __shfl_xor(a2, off);
+        a3 += __shfl_xor(a3, off);
+    }
+    if (q == 0) {
+        G[k] = a0;
+        G[16 + k] = a1;
+        G[32 + k] = a2;
+        G[48 + k] = a3;
+    }
+}
+
+// Pair q (0 <= q < nA (nA-1)/2) -> angular entries (j < k), enumerated by k then j.
+__device__ __forceinline__ void pair_of(int q, int& j, int& k)
+{
+    int kk = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+    while (kk * (kk - 1) / 2 > q) --kk;
+    while ((kk + 1) * kk / 2 <= q) ++kk;
+    k = kk;
+    j = q - kk * (kk - 1) / 2;
+}
+
+// Angular features added into Gang[0..319] (LDS, zeroed beforehand).  One lane
+// per neighbour pair; the 32 terms of a pair go to the block of its element
+// pair through LDS atomics (one wave per atom, so the order is fixed).
+__device__ void angular_features(const Env& E, float* Gang)
+{
+    const int lane = lane_id();
+    const int nA = E.nA;
+    const int np = nA * (nA - 1) / 2;
+    for (int q = lane; q < np; q += 64) {
+        int j, k;
+        pair_of(q, j, k);
+        const int ej = E.ang[j], ek = E.ang[k];
+        const float4 gj = E.geo[ej], gk = E.geo[ek];
+        const float c = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
+        const float cp = kCosScale * c;
+        const float sp = sqrtf(fmaxf(0.f, 1.f - cp * cp));
+        const float w = kTwoPowM31 * E.afc[j].x * E.afc[k].x;
+        const float rbar = 0.5f * (gj.w + gk.w);
+        float B[kNumShells];
+#pragma unroll
+        for (int m = 0; m < kNumShells; ++m) {
+            const float x = rbar - (0.9f + 0.65f * (float)m);
+            B[m] = w * __expf(-kEtaAng * x * x);
+        }
+        float* dst = Gang + 32 * pair_type(E.info[ej] & 3, E.info[ek] & 3);
+#pragma unroll
+        for (int n = 0; n < kNumSectors; ++n) {
+            float u = 1.f + cp * kSecCos[n] + sp * kSecSin[n];
+            u = u * u;  // ^2
+            u = u * u;  // ^4
+            u = u * u;  // ^8
+            u = u * u;  // ^16
+            u = u * u;  // ^32
+#pragma unroll
+            for (int m = 0; m < kNumShells; ++m) atomicAdd(dst + 8 * m + n, u * B[m]);
+        }
+    }
+}
+
+// Adjoint of the descriptors for the wave's atom a: given g = dE_a/dG_a
+// (LDS), accumulates the force on every neighbour within 5.2 A due to E_a into
+// facc[3 * entry] (LDS).  Radial entries are owned by one lane each (plain
+// store); the angular pairs then add with LDS atomics.  The caller separates
+// the two phases with a barrier.
+__device__ void adjoint_radial(const Env& E, const float* g, float* facc)
+{
+    const int lane = lane_id();
+    const int nR = E.nR;
+    for (int e = lane; e < nR; e += 64) {
+        const float4 ge = E.geo[e];
+        const float2 f = E.fcr[e];
+        const float* gs = g + 16 * (E.info[e] & 3);
+        float dEdr = 0.f;
+#pragma unroll
+        for (int k = 0; k < kNumRadial; ++k) {
+            const float x = ge.w - (0.9f + 0.28f * (float)k);
+            const float ex = __expf(-kEtaRad * x * x);
+            dEdr += gs[k] * ex * (f.y - 2.f * kEtaRad * x * f.x);
+        }
+        facc[3 * e + 0] = -dEdr * ge.x;
+        facc[3 * e + 1] = -dEdr * ge.y;
+        facc[3 * e + 2] = -dEdr * ge.z;
+    }
+}
+
+__device__ void adjoint_angular(const Env& E, const float* g, float* facc)
+{
+    const int lane = lane_id();
+    const int nA = E.nA;
+    const int np = nA * (nA - 1) / 2;
+    for (int q = lane; q < np; q += 64) {
+        int j, k;
+        pair_of(q, j, k);
+        const int ej = E.ang[j], ek = E.ang[k];
+        const float4 gj = E.geo[ej], gk = E.geo[ek];
+        const float2 fj = E.afc[j], fk = E.afc[k];
+        const float c = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
+        const float cp = kCosScale * c;
+        const float sp = sqrtf(fmaxf(0.f, 1.f - cp * cp));
+        const float rbar = 0.5f * (gj.w + gk.w);
+        const float* gb = g + 64 + 32 * pair_type(E.info[ej] & 3, E.info[ek] & 3);
+        // P_n = sum_m g_mn B_m, Q_n = sum_m g_mn dB_m/drbar
+        float B[kNumShells], dB[kNumShells];
+#pragma unroll
+        for (int m = 0; m < kNumShells; ++m) {
+            const float x = rbar - (0.9f + 0.65f * (float)m);
+            B[m] = __expf(-kEtaAng * x * x);
+            dB[m] = -2.f * kEtaAng * x * B[m];
+        }
+        float Et = 0.f, dEdcp = 0.f, dEdrb = 0.f;
+        const float inv_sp = 1.f / sp;
+#pragma unroll
+        for (int n = 0; n < kNumSectors; ++n) {
+            float P = 0.f, Q = 0.f;
+#pragma unroll
+            for (int m = 0; m < kNumShells; ++m) {
+                const float gv = gb[8 * m + n];
+                P += gv * B[m];
+                Q += gv * dB[m];
+            }
+            const float ct = kSecCos[n], st = kSecSin[n];
+            const float u = 1.f + cp * ct + sp * st;
+            float u2 = u * u, u4 = u2 * u2, u8 = u4 * u4, u16 = u8 * u8;
+            const float u31 = u16 * u8 * u4 * u2 * u;
+            const float A = u31 * u;
+            const float dA = 32.f * u31 * (ct - cp * st * inv_sp);
+            Et += A * P;
+            dEdcp += dA * P;
+            dEdrb += A * Q;
+        }
+        // E_t = w * sum_n A_n P_n with w = 2^-31 fc_j fc_k
+        const float pre = kTwoPowM31;
+        const float ff = fj.x * fk.x;
+        const float dEdc = pre * ff * kCosScale * dEdcp;
+        const float dEdrj = pre * (Et * fj.y * fk.x + 0.5f * ff * dEdrb);
+        const float dEdrk = pre * (Et * fj.x * fk.y + 0.5f * ff * dEdrb);
+        const float ij = 1.f / gj.w, ik = 1.f / gk.w;
+        // gradient of E_a with respect to x_j and x_k; the force is its negative
+        const float gjx = dEdrj * gj.x + dEdc * (gk.x - c * gj.x) * ij;
+        const float gjy = dEdrj * gj.y + dEdc * (gk.y - c * gj.y) * ij;
+        const float gjz = dEdrj * gj.z + dEdc * (gk.z - c * gj.z) * ij;
+        const float gkx = dEdrk * gk.x + dEdc * (gj.x - c * gk.x) * ik;
+        const float gky = dEdrk * gk.y + dEdc * (gj.y - c * gk.y) * ik;
+        const float gkz = dEdrk * gk.z + dEdc * (gj.z - c * gk.z) * ik;
+        atomicAdd(&facc[3 * ej + 0], -gjx);
+        atomicAdd(&facc[3 * ej + 1], -gjy);
+        atomicAdd(&facc[3 * ej + 2], -gjz);
+        atomicAdd(&facc[3 * ek + 0], -gkx);
+        atomicAdd(&facc[3 * ek + 1], -gky);
+        atomicAdd(&facc[3 * ek + 2], -gkz);
+    }
+}
+
+// Writes the per-slot forces of atom a to HBM (zero for slots beyond 5.2 A).
+__device__ void store_slot_forces(const Sys& S, int a, const Env& E, const float* facc)
+{
+    const int lane = lane_id();
+    const size_t base = (size_t)a * S.cap;
+    for (int s = lane; s < E.nS; s += 64) {
+        const int e = E.smap[s];
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e != kNoEntry) v = make_float4(facc[3 * e], facc[3 * e + 1], facc[3 * e + 2], 0.f);
+        S.fslot[base + s] = v;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Network on a tile of up to T atoms of one element (workgroup-wide).
+// ------------------------------------------------------------------------
+
+// LDS row strides (elements) of the activation buffers.
+constexpr int kLdG = kNumFeat + 4;  // fp32 G / dE/dG rows
+constexpr int kLd1 = kH1 + 8;       // bf16 rows
+constexpr int kLd2 = kH2 + 8;
+constexpr int kLd3 = kH3 + 8;
+constexpr int kLdF1 = kH1 + 4;      // fp32 rows
+constexpr int kLdF2 = kH2 + 4;
+constexpr int kLdF3 = kH3 + 4;
+
+// out[t][o] = sum_k in[t][k] * Wm[k][o] (+ epilogue) for o < M, t < T.
+// Thread = (output o, group of 4 atoms).
+template <int T, int K, int M, int EPI>
+__device__ __forceinline__ void dense_f32(const float* in, int ldi, const float* __restrict__ Wm,
+                                          const float* __restrict__ bias, float* out, int ldo, float* aux,
+                                          int ldaux, int tid, int nthr)
+{
+    constexpr int NG = (T + 3) / 4;
+    for (int idx = tid; idx < M * NG; idx += nthr) {
+        const int o = idx % M, ag = idx / M;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < K; k += 4) {
+            const float w0 = Wm[(k + 0) * M + o], w1 = Wm[(k + 1) * M + o];
+            const float w2 = Wm[(k + 2) * M + o], w3 = Wm[(k + 3) * M + o];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float4 x = *reinterpret_cast<const float4*>(in + (4 * ag + t) * ldi + k);
+                acc[t] += x.x * w0 + x.y * w1 + x.z * w2 + x.w * w3;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int at = 4 * ag + t;
+            if (at >= T) break;
+            float v = acc[t];
+            if (EPI == 0) {  // forward: z = v + b; out = celu(z); aux = celu'(z)
+                const float z = v + bias[o];
+                out[at * ldo + o] = celu_f(z);
+                aux[at * ldaux + o] = celu_d(z);
+            } else if (EPI == 1) {  // backward: out = v * aux
+                out[at * ldo + o] = v * aux[at * ldaux + o];
+            } else {  // plain store
+                out[at * ldo + o] = v;
+            }
+        }
+    }
+}
+
+// Per-tile LDS of the FP32 network (rows of T atoms).
+template <int T>
+struct MlpF32Smem {
+    float h1[T * kLdF1], d1[T * kLdF1];
+    float h2[T * kLdF2], d2[T * kLdF2];
+    float h3[T * kLdF3], d3[T * kLdF3];
+};
+
+// FP32 network forward + input gradient on VALU.  G: [T][kLdG] fp32 in LDS,
+// replaced by dE/dG when GRAD.  E[T] receives the atom energies.
+template <int T, bool GRAD>
+__device__ void mlp_f32(const float* __restrict__ w, float* G, MlpF32Smem<T>& sm, float* E, int tid, int nthr)
+{
+    using L = W32Layout;
+    dense_f32<T, kNumFeat, kH1, 0>(G, kLdG, w + L::Wt1, w + L::B1, sm.h1, kLdF1, sm.d1, kLdF1, tid, nthr);
+    __syncthreads();
+    dense_f32<T, kH1, kH2, 0>(sm.h1, kLdF1, w + L::Wt2, w + L::B2, sm.h2, kLdF2, sm.d2, kLdF2, tid, nthr);
+    __syncthreads();
+    dense_f32<T, kH2, kH3, 0>(sm.h2, kLdF2, w + L::Wt3, w + L::B3, sm.h3, kLdF3, sm.d3, kLdF3, tid, nthr);
+    __syncthreads();
+    // output layer: one wave per atom
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int t = wave; t < T; t += nw) {
+        float s = 0.f;
+        for (int o = lane; o < kH3; o += 64) s += w[L::W4 + o] * sm.h3[t * kLdF3 + o];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) E[t] = s + w[L::B4];
+    }
+    if (!GRAD) return;
+    // delta3 = celu'(z3) * W4, in place of d3
+    for (int idx = tid; idx < T * kH3; idx += nthr) {
+        const int t = idx / kH3, o = idx % kH3;
+        sm.d3[t * kLdF3 + o] *= w[L::W4 + o];
+    }
+    __syncthreads();
+    // delta2 = celu'(z2) * (W3^T delta3): W3 is [96][128] = [k][m]
+    dense_f32<T, kH3, kH2, 1>(sm.d3, kLdF3, w + L::W3, nullptr, sm.h2, kLdF2, sm.d2, kLdF2, tid, nthr);
+    __syncthreads();
+    dense_f32<T, kH2, kH1, 1>(sm.h2, kLdF2, w + L::W2, nullptr, sm.h1, kLdF1, sm.d1, kLdF1, tid, nthr);
+    __syncthreads();
+    dense_f32<T, kH1, kNumFeat, 2>(sm.h1, kLdF1, w + L::W1, nullptr, G, kLdG, nullptr, 0, tid, nthr);
+    __syncthreads();
+}
+
+// Per-tile LDS of the MFMA network (16 atom columns; unused columns are
+// zero).  Single-pass BF16 keeps the activations as BF16; the split mode
+// keeps them in FP32 and splits every operand into hi + lo BF16 parts.
+template <int T, bool SPLIT>
+struct MlpMfmaSmem {
+    using AT = typename std::conditional<SPLIT, float, __bf16>::type;
+    static constexpr int LD1 = SPLIT ? kLdF1 : kLd1;
+    static constexpr int LD2 = SPLIT ? kLdF2 : kLd2;
+    static constexpr int LD3 = SPLIT ? kLdF3 : kLd3;
+    AT h1[T * LD1];         // h1, later delta1
+    AT h2[T * LD2];         // h2, later delta2
+    AT h3[T * LD3];         // delta3
+    float d1[T * kLdF1];    // celu'(z1)
+    float d2[T * kLdF2];    // celu'(z2)
+    float ep[8 * 16];       // output-layer partial sums per (m tile, atom)
+};
+
+__device__ __forceinline__ bf16x8 cvt8(const float4 x0, const float4 x1)
+{
+    bf16x8 b;
+    b[0] = (__bf16)x0.x; b[1] = (__bf16)x0.y; b[2] = (__bf16)x0.z; b[3] = (__bf16)x0.w;
+    b[4] = (__bf16)x1.x; b[5] = (__bf16)x1.y; b[6] = (__bf16)x1.z; b[7] = (__bf16)x1.w;
+    return b;
+}
+
+// hi = bf16(x), lo = bf16(x - hi) for 8 values
+__device__ __forceinline__ void split8(const float* p, bf16x8& hi, bf16x8& lo)
+{
+    const float4 x0 = *reinterpret_cast<const float4*>(p);
+    const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+    hi = cvt8(x0, x1);
+    const float4 r0 = make_float4(x0.x - (float)hi[0], x0.y - (float)hi[1], x0.z - (float)hi[2], x0.w - (float)hi[3]);
+    const float4 r1 = make_float4(x1.x - (float)hi[4], x1.y - (float)hi[5], x1.z - (float)hi[6], x1.w - (float)hi[7]);
+    lo = cvt8(r0, r1);
+}
+
+// One 16 x 16 output tile: rows = outputs of fragment row mt, columns =
+// atoms (columns >= T are zero).  A from pre-swizzled weight fragments
+// (HBM/L2), B from LDS rows.  SPLIT: D = A_hi B_hi + A_hi B_lo + A_lo B_hi
+// (FP32 accumulation).
+template <int T, int KT, bool SPLIT, typename TB>
+__device__ __forceinline__ floatx4 mfma_tile(const bf16x8* __restrict__ fhi, const bf16x8* __restrict__ flo,
+                                             const TB* act, int ld, int lane)
+{
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int col = lane & 15, kq = (lane >> 4) * 8;
+    const bool live = col < T;
+    const bf16x8 zero = {};
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+        const bf16x8 a = fhi[kt * 64 + lane];
+        const TB* p = act + (live ? col : 0) * ld + kt * 32 + kq;
+        if constexpr (SPLIT) {
+            bf16x8 bh, bl;
+            split8(reinterpret_cast<const float*>(p), bh, bl);
+            if (!live) {
+                bh = zero;
+                bl = zero;
+            }
+            const bf16x8 al = flo[kt * 64 + lane];
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+        } else {
+            bf16x8 b;
+            if constexpr (std::is_same<TB, float>::value) {
+                const float* q = reinterpret_cast<const float*>(p);
+                b = cvt8(*reinterpret_cast<const float4*>(q), *reinterpret_cast<const float4*>(q + 4));
+            } else {
+                b = *reinterpret_cast<const bf16x8*>(p);
+            }
+            if (!live) b = zero;
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// MFMA network forward + input gradient for the T atoms of a tile (MFMA
+// columns >= T are zero).  G: [T][kLdG] fp32, replaced by dE/dG when GRAD.
+// fr points at the element's hi fragments; its lo fragments follow after
+// FragLayout::Count fragments.
+template <int T, bool SPLIT, bool GRAD>
+__device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__ fr, float* G,
+                         MlpMfmaSmem<T, SPLIT>& sm, float* E, int tid, int nthr)
+{
+    using L = W32Layout;
+    using F = FragLayout;
+    using S = MlpMfmaSmem<T, SPLIT>;
+    using AT = typename S::AT;
+    const bf16x8* lo = fr + F::Count * 64;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    const int col = lane & 15, rq = (lane >> 4) * 4;
+    const bool live = col < T;
+    // layer 1: 160 x 384
+    for (int mt = wave; mt < 10; mt += nw) {
+        const int f = (F::F1 + mt * 12) * 64;
+        const floatx4 acc = mfma_tile<T, 12, SPLIT>(fr + f, lo + f, G, kLdG, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mt * 16 + rq + i;
+            const float z = acc[i] + w[L::B1 + o];
+            if (live) {
+                sm.h1[col * S::LD1 + o] = (AT)celu_f(z);
+                sm.d1[col * kLdF1 + o] = celu_d(z);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2: 128 x 160
+    for (int mt = wave; mt < 8; mt += nw) {
+        const int f = (F::F2 + mt * 5) * 64;
+        const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1, S::LD1, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mt * 16 + rq + i;
+            const float z = acc[i] + w[L::B2 + o];
+            if (live) {
+                sm.h2[col * S::LD2 + o] = (AT)celu_f(z);
+                sm.d2[col * kLdF2 + o] = celu_d(z);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 3: 96 x 128, fused with the output layer and delta3 = celu'(z3) W4
+    for (int mt = wave; mt < 6; mt += nw) {
+        const int f = (F::F3 + mt * 4) * 64;
+        const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2, S::LD2, lane);
+        float part = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mt * 16 + rq + i;
+            const float z = acc[i] + w[L::B3 + o];
+            const float w4 = w[L::W4 + o];
+            part += w4 * celu_f(z);
+            if (live) sm.h3[col * S::LD3 + o] = (AT)(celu_d(z) * w4);
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (lane < 16) sm.ep[mt * 16 + lane] = part;
+    }
+    __syncthreads();
+    if (tid < T) {
+        float s = w[L::B4];
+        for (int mt = 0; mt < 6; ++mt) s += sm.ep[mt * 16 + tid];
+        E[tid] = s;
+    }
+    if (!GRAD) return;
+    // delta2 = celu'(z2) * W3^T delta3   (128 x 96)
+    for (int mt = wave; mt < 8; mt += nw) {
+        const int f = (F::B3 + mt * 3) * 64;
+        const floatx4 acc = mfma_tile<T, 3, SPLIT>(fr + f, lo + f, sm.h3, S::LD3, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mt * 16 + rq + i;
+            if (live) sm.h2[col * S::LD2 + o] = (AT)(acc[i] * sm.d2[col * kLdF2 + o]);
+        }
+    }
+    __syncthreads();
+    // delta1 = celu'(z1) * W2^T delta2   (160 x 128)
+    for (int mt = wave; mt < 10; mt += nw) {
+        const int f = (F::B2 + mt * 4) * 64;
+        const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2, S::LD2, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mt * 16 + rq + i;
+            if (live) sm.h1[col * S::LD1 + o] = (AT)(acc[i] * sm.d1[col * kLdF1 + o]);
+        }
+    }
+    __syncthreads();
+    // dE/dG = W1^T delta1   (384 x 160)
+    for (int mt = wave; mt < 24; mt += nw) {
+        const int f = (F::B1 + mt * 5) * 64;
+        const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1, S::LD1, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (live) G[col * kLdG + mt * 16 + rq + i] = acc[i];
+    }
+    __syncthreads();
+}
+
+}  // namespace nnp

@@ -1,0 +1,147 @@
+// nnp_internal.h -- device-side data layout shared by the HIP kernels and the
+// host runtime of the NNP library (never exposed through the C ABI).
+//
+// Data layout in HBM (internal atom order: element-major H, C, N, O; within an
+// element by molecule; within a molecule by a Morton key of the initial
+// positions, so consecutive atoms of a tile are spatial neighbours):
+//   pos    double4[n]    x, y, z (A), w = element as a double  (FP64 master)
+//   vel    double4[n]    A/fs
+//   frc    double4[n]    gathered FP64 forces (eV/A)
+//   ref    float4[n]     positions at the last pair-list rebuild
+//   nbr    int[n][cap]   pair list (cutoff 5.2 + skin), ascending internal index
+//   rev    int[n][cap]   position of atom a in the list of its neighbour j
+//   fslot  float4[n][cap] force on neighbour nbr[a][s] due to E_a (eV/A)
+//   Ei     float[n]      per-atom energies of the last evaluation
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nnp {
+
+constexpr int kNumSpecies = 4;
+constexpr int kNumRadial = 16;
+constexpr int kNumShells = 4;
+constexpr int kNumSectors = 8;
+constexpr int kNumFeat = 384;   // 4 * 16 radial + 10 * 32 angular
+constexpr int kH1 = 160, kH2 = 128, kH3 = 96;
+
+constexpr float kCutRad = 5.2f;
+constexpr float kCutAng = 3.5f;
+constexpr float kEtaRad = 16.0f;
+constexpr float kEtaAng = 8.0f;
+constexpr float kCosScale = 0.95f;
+constexpr float kCeluAlpha = 0.1f;
+constexpr double kKappa = 9.64853321e-3;  // A fs^-2 per eV A^-1 amu^-1
+
+constexpr int kRadMax = 160;  // radial entries per atom held in LDS
+constexpr int kAngMax = 96;   // angular entries per atom held in LDS
+constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits)
+constexpr int kRing = 4096;   // energy log ring (steps)
+
+// Per-element FP32 weight block (floats).  Forward dense layers read the
+// transposed matrices ([in][out], coalesced over outputs), the backward ones
+// the original [out][in] rows (coalesced over inputs).
+struct W32Layout {
+    static constexpr int Wt1 = 0;                    // [384][160]
+    static constexpr int W1 = Wt1 + kNumFeat * kH1;  // [160][384]
+    static constexpr int Wt2 = W1 + kH1 * kNumFeat;  // [160][128]
+    static constexpr int W2 = Wt2 + kH1 * kH2;       // [128][160]
+    static constexpr int Wt3 = W2 + kH2 * kH1;       // [128][96]
+    static constexpr int W3 = Wt3 + kH2 * kH3;       // [96][128]
+    static constexpr int W4 = W3 + kH3 * kH2;        // [96]
+    static constexpr int B1 = W4 + kH3;              // [160]
+    static constexpr int B2 = B1 + kH1;              // [128]
+    static constexpr int B3 = B2 + kH2;              // [96]
+    static constexpr int B4 = B3 + kH3;              // [1]
+    static constexpr int Stride = ((B4 + 1 + 63) / 64) * 64;
+};
+
+// Per-element BF16 MFMA A-operand fragments (16 rows x 32 k per fragment,
+// 64 lanes x 8 values).  Fragment (mt, kt) of a layer sits at
+// base + mt * KT + kt.
+struct FragLayout {
+    static constexpr int F1 = 0;               // W1    M=160 K=384: 10 x 12
+    static constexpr int F2 = F1 + 10 * 12;    // W2    M=128 K=160:  8 x 5
+    static constexpr int F3 = F2 + 8 * 5;      // W3    M=96  K=128:  6 x 4
+    static constexpr int B3 = F3 + 6 * 4;      // W3^T  M=128 K=96:   8 x 3
+    static constexpr int B2 = B3 + 8 * 3;      // W2^T  M=160 K=128: 10 x 4
+    static constexpr int B1 = B2 + 10 * 4;     // W1^T  M=384 K=160: 24 x 5
+    static constexpr int Count = B1 + 24 * 5;  // 368 fragments per element
+};
+
+// Device step state.  Written only by the last workgroup of the integration
+// kernel (completion-counter pattern), read by every kernel of the next step.
+struct StepState {
+    int step;          // steps completed
+    int age;           // evaluations since the last rebuild
+    int lists_valid;   // 0 until the first build, and after positions are set from outside
+    int viol[2];       // viol[n & 1]: an atom moved more than skin/2 before evaluation n
+    int overflow;      // a capacity (pair list, radial or angular LDS entries) was exceeded
+    int nonfinite;     // a non-finite energy or force was produced
+    int last_slot;     // step index of the most recent evaluation (ring slot = index % kRing)
+    unsigned done;     // completion counter of the integration kernel
+    int max_ns, max_nr, max_na;  // largest pair-list / radial / angular count seen
+    int pad;
+    long long n_eval, n_rebuild, n_forced;
+};
+
+struct Sys {
+    int n, nmol, cap, ntiles;
+    int rebuild_every;
+    float rlist2;      // (5.2 + skin)^2
+    float half_skin2;  // (skin / 2)^2
+    double4* pos;
+    double4* vel;
+    double4* frc;
+    float4* ref;
+    const double* kinv;  // kappa / m
+    const double* mass;
+    const int* mol;
+    const int2* mrange;  // [nmol * 4] internal index range of each element of a molecule
+    const int4* tiles;   // {first atom, count, element, 0}
+    int* nbr;
+    int* ncnt;
+    int* rev;
+    float4* fslot;
+    float* Ei;
+    double* Uring;  // [kRing][nmol]
+    double* Kring;
+    double* Eacc;   // [nmol] accumulators of the running evaluation
+    double* Kacc;
+    double* Ecur;   // [nmol] potential / kinetic energy of the most recent evaluation
+    double* Kcur;
+    const int* perm;  // [n] internal -> caller index
+    double* stage;    // [3 n] staging for positions in caller order
+    StepState* st;
+    const float* w32;   // 4 * W32Layout::Stride floats
+    const void* wfrag;  // 4 * FragLayout::Count fragments of 1 KiB
+    // plain-path intermediates
+    float* G;   // [n][384]
+    float* dG;  // [n][384]
+};
+
+// True when the evaluation that reads this state has to rebuild the pair list.
+__device__ __forceinline__ bool rebuild_due(const StepState* st, int rebuild_every)
+{
+    return !st->lists_valid || st->viol[st->step & 1] || st->age >= rebuild_every;
+}
+
+__device__ __forceinline__ int pair_type(int a, int b)
+{
+    // unordered element pair index: HH HC HN HO CC CN CO NN NO OO
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    return lo * 4 - (lo * (lo - 1)) / 2 + (hi - lo);
+}
+
+__device__ __forceinline__ float celu_f(float z)
+{
+    return z > 0.0f ? z : kCeluAlpha * (__expf(z * (1.0f / kCeluAlpha)) - 1.0f);
+}
+
+__device__ __forceinline__ float celu_d(float z)
+{
+    return z > 0.0f ? 1.0f : __expf(z * (1.0f / kCeluAlpha));
+}
+
+}  // namespace nnp

@@ -1,0 +1,486 @@
+// nnp_kernels.hip -- the HIP kernels of one MD step and their launchers.
+//
+// Fused path (one launch per evaluation): a workgroup of T wavefronts takes a
+// tile of T atoms of one element; wave w owns atom w of the tile through the
+// pair-list rebuild (when due), the environment load, the descriptors, the
+// network (workgroup-wide) and the adjoint.  Everything between the positions
+// and the per-slot forces lives in LDS.
+//
+// Plain path (one launch per stage): pair list, descriptors -> G in HBM,
+// network -> dE/dG in HBM, adjoint -> per-slot forces.
+//
+// Both paths end with k_gather_integrate: per-atom force gather in FP64, the
+// velocity-Verlet update in FP64, per-molecule FP64 energy sums, and the
+// device step-state update by the last workgroup (completion counter).
+#include "nnp_device.h"
+#include "nnp_launch.h"
+
+namespace nnp {
+
+// ---------------------------------------------------------------- fused ---
+
+// Network arithmetic: 0 = FP32 VALU, 1 = BF16 MFMA, 2 = split BF16 MFMA (x3).
+template <int T, int MODE>
+struct MlpSmemOf {
+    using type = MlpF32Smem<T>;
+};
+template <int T>
+struct MlpSmemOf<T, 1> {
+    using type = MlpMfmaSmem<T, false>;
+};
+template <int T>
+struct MlpSmemOf<T, 2> {
+    using type = MlpMfmaSmem<T, true>;
+};
+
+template <int T, int MODE, bool GRAD>
+__device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typename MlpSmemOf<T, MODE>::type& sm,
+                                        float* E, int tid)
+{
+    const float* w = S.w32 + (size_t)elem * W32Layout::Stride;
+    if constexpr (MODE == 0) {
+        mlp_f32<T, GRAD>(w, G, sm, E, tid, 64 * T);
+    } else {
+        const bf16x8* fr = reinterpret_cast<const bf16x8*>(S.wfrag) + (size_t)elem * 2 * FragLayout::Count * 64;
+        mlp_mfma<T, MODE == 2, GRAD>(w, fr, G, sm, E, tid, 64 * T);
+    }
+}
+
+template <int T, int MODE>
+struct FusedSmem {
+    Env env[T];
+    float G[T * kLdG];
+    union {
+        typename MlpSmemOf<T, MODE>::type m;
+        float facc[T * 3 * kRadMax];
+    } u;
+    float E[16];
+};
+
+template <int T, int MODE, bool GRAD>
+__global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
+{
+    __shared__ __attribute__((aligned(16))) FusedSmem<T, MODE> sm;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int4 tile = S.tiles[blockIdx.x];
+    const int a = tile.x + wave;
+    const bool act = wave < tile.y;
+    const bool rb = rebuild_due(S.st, S.rebuild_every);
+    Env& E = sm.env[wave];
+    float* Grow = sm.G + wave * kLdG;
+
+    if (act) {
+        if (rb)
+            build_list_env(S, a, E);
+        else
+            load_env(S, a, E);
+    }
+    for (int i = tid; i < T * kLdG; i += 64 * T) sm.G[i] = 0.f;
+    __syncthreads();
+    if (act) {
+        radial_features(E, Grow);
+        angular_features(E, Grow + 64);
+    }
+    __syncthreads();
+    run_mlp<T, MODE, GRAD>(S, tile.z, sm.G, sm.u.m, sm.E, tid);
+    __syncthreads();
+    if (act && lane == 0) S.Ei[a] = sm.E[wave];
+    if (GRAD) {
+        float* fa = sm.u.facc + wave * 3 * kRadMax;
+        if (act) adjoint_radial(E, Grow, fa);
+        __syncthreads();
+        if (act) adjoint_angular(E, Grow, fa);
+        __syncthreads();
+        if (act) store_slot_forces(S, a, E, fa);
+    }
+}
+
+// ---------------------------------------------------------------- plain ---
+
+// Pair lists of all atoms (when due).  One wave per atom.
+__global__ __launch_bounds__(256) void k_lists(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (a < S.n) build_list(S, a);
+}
+
+// Descriptors of all atoms into S.G (internal order).  One wave per atom.
+__global__ __launch_bounds__(256) void k_descriptors(Sys S)
+{
+    __shared__ Env env[4];
+    __shared__ __attribute__((aligned(16))) float G[4 * kLdG];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = blockIdx.x * 4 + wave;
+    float* Grow = G + wave * kLdG;
+    for (int i = lane; i < kLdG; i += 64) Grow[i] = 0.f;
+    if (a < S.n) load_env(S, a, env[wave]);
+    __syncthreads();
+    if (a < S.n) {
+        radial_features(env[wave], Grow);
+        angular_features(env[wave], Grow + 64);
+    }
+    __syncthreads();
+    if (a < S.n)
+        for (int i = lane; i < kNumFeat; i += 64) S.G[(size_t)a * kNumFeat + i] = Grow[i];
+}
+
+// Network of one tile of atoms: G from HBM, dE/dG (when GRAD) and E_i to HBM.
+template <int T, int MODE, bool GRAD>
+__global__ __launch_bounds__(64 * T) void k_mlp(Sys S)
+{
+    __shared__ __attribute__((aligned(16))) float G[T * kLdG];
+    __shared__ __attribute__((aligned(16))) typename MlpSmemOf<T, MODE>::type u;
+    __shared__ float E[16];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int4 tile = S.tiles[blockIdx.x];
+    for (int i = tid; i < T * kLdG; i += 64 * T) {
+        const int t = i / kLdG, f = i % kLdG;
+        G[i] = (t < tile.y && f < kNumFeat) ? S.G[(size_t)(tile.x + t) * kNumFeat + f] : 0.f;
+    }
+    __syncthreads();
+    run_mlp<T, MODE, GRAD>(S, tile.z, G, u, E, tid);
+    __syncthreads();
+    if (wave < tile.y && lane == 0) S.Ei[tile.x + wave] = E[wave];
+    if (GRAD)
+        for (int i = tid; i < T * kNumFeat; i += 64 * T) {
+            const int t = i / kNumFeat, f = i % kNumFeat;
+            if (t < tile.y) S.dG[(size_t)(tile.x + t) * kNumFeat + f] = G[t * kLdG + f];
+        }
+}
+
+// Adjoint of all atoms from S.dG.  One wave per atom.
+__global__ __launch_bounds__(256) void k_adjoint(Sys S)
+{
+    __shared__ Env env[4];
+    __shared__ __attribute__((aligned(16))) float g[4 * kNumFeat];
+    __shared__ float facc[4 * 3 * kRadMax];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = blockIdx.x * 4 + wave;
+    float* gr = g + wave * kNumFeat;
+    float* fa = facc + wave * 3 * kRadMax;
+    if (a < S.n) {
+        load_env(S, a, env[wave]);
+        for (int i = lane; i < kNumFeat; i += 64) gr[i] = S.dG[(size_t)a * kNumFeat + i];
+    }
+    __syncthreads();
+    if (a < S.n) adjoint_radial(env[wave], gr, fa);
+    __syncthreads();
+    if (a < S.n) adjoint_angular(env[wave], gr, fa);
+    __syncthreads();
+    if (a < S.n) store_slot_forces(S, a, env[wave], fa);
+}
+
+// --------------------------------------------------- gather + integrate ---
+
+__device__ __forceinline__ double atomic_read(double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// mode 0: evaluation only (forces, energies; no integration, step unchanged)
+// mode 1: second half kick (completes a step), step += 1
+// mode 2: as 1, then the first half kick and drift of the next step
+__global__ __launch_bounds__(256) void k_gather_integrate(Sys S, double dt, int mode)
+{
+    __shared__ double sE[16], sK[16];
+    __shared__ int sM[16];
+    __shared__ int last;
+    const int tid = threadIdx.x, sub = tid & 15, la = tid >> 4;
+    const int a = blockIdx.x * 16 + la;
+    StepState* st = S.st;
+    const bool rb = rebuild_due(st, S.rebuild_every);
+    const int nstep = st->step;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (a < S.n) {
+        const int cnt = S.ncnt[a];
+        const size_t base = (size_t)a * S.cap;
+        for (int s = sub; s < cnt; s += 16) {
+            const int j = S.nbr[base + s];
+            int r;
+            if (rb) {
+                const int* lj = S.nbr + (size_t)j * S.cap;
+                int lo = 0, hi = S.ncnt[j] - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (lj[mid] < a)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                r = lo;
+                S.rev[base + s] = r;
+            } else {
+                r = S.rev[base + s];
+            }
+            const float4 fin = S.fslot[(size_t)j * S.cap + r];
+            const float4 fout = S.fslot[base + s];
+            fx += (double)fin.x - (double)fout.x;
+            fy += (double)fin.y - (double)fout.y;
+            fz += (double)fin.z - (double)fout.z;
+        }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    if (sub == 0) {
+        if (a < S.n) {
+            double4 v = S.vel[a];
+            double4 p = S.pos[a];
+            const double ki = S.kinv[a];
+            const double e = (double)S.Ei[a];
+            S.frc[a] = make_double4(fx, fy, fz, 0.0);
+            if (mode >= 1) {
+                v.x += 0.5 * dt * ki * fx;
+                v.y += 0.5 * dt * ki * fy;
+                v.z += 0.5 * dt * ki * fz;
+            }
+            const double k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
+            if (mode == 2) {
+                v.x += 0.5 * dt * ki * fx;
+                v.y += 0.5 * dt * ki * fy;
+                v.z += 0.5 * dt * ki * fz;
+                p.x += dt * v.x;
+                p.y += dt * v.y;
+                p.z += dt * v.z;
+                S.pos[a] = p;
+                const float4 r0 = S.ref[a];
+                const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
+                if (dx * dx + dy * dy + dz * dz > S.half_skin2) atomicOr(&st->viol[(nstep + 1) & 1], 1);
+            }
+            if (mode >= 1) S.vel[a] = v;
+            if (!isfinite(fx + fy + fz + e)) atomicOr(&st->nonfinite, 1);
+            sE[la] = e;
+            sK[la] = k;
+            sM[la] = S.mol[a];
+        } else {
+            sE[la] = 0.0;
+            sK[la] = 0.0;
+            sM[la] = -1;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int i = 0;
+        while (i < 16) {
+            const int m = sM[i];
+            if (m < 0) {
+                ++i;
+                continue;
+            }
+            double e = 0.0, k = 0.0;
+            while (i < 16 && sM[i] == m) {
+                e += sE[i];
+                k += sK[i];
+                ++i;
+            }
+            atomicAdd(&S.Eacc[m], e);
+            atomicAdd(&S.Kacc[m], k);
+        }
+        __threadfence();
+        const unsigned prev = atomicAdd(&st->done, 1u);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // the evaluation just reduced belongs to step index nstep (mode 0) or, after
+    // the kick that completes step nstep -> nstep + 1, to index nstep + 1
+    const int eval_index = mode >= 1 ? nstep + 1 : nstep;
+    const int slot = eval_index % kRing;
+    for (int m = tid; m < S.nmol; m += blockDim.x) {
+        const double e = atomic_read(&S.Eacc[m]);
+        const double k = atomic_read(&S.Kacc[m]);
+        S.Uring[(size_t)slot * S.nmol + m] = e;
+        S.Kring[(size_t)slot * S.nmol + m] = k;
+        S.Ecur[m] = e;
+        S.Kcur[m] = k;
+        if (!isfinite(e)) atomicOr(&st->nonfinite, 1);
+        __hip_atomic_store(&S.Eacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&S.Kacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) {
+        st->n_eval += 1;
+        if (rb) {
+            st->n_rebuild += 1;
+            if (st->lists_valid && st->age < S.rebuild_every) st->n_forced += 1;
+            st->age = 0;
+            st->lists_valid = 1;
+        }
+        st->age += 1;
+        st->viol[nstep & 1] = 0;
+        st->last_slot = eval_index;
+        if (mode >= 1) st->step = nstep + 1;
+        st->done = 0u;
+    }
+}
+
+// First half kick and drift of a step (starts a block of steps).
+__global__ __launch_bounds__(256) void k_kickdrift(Sys S, double dt)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int nstep = S.st->step;
+    const double4 f = S.frc[a];
+    double4 v = S.vel[a];
+    double4 p = S.pos[a];
+    const double ki = S.kinv[a];
+    v.x += 0.5 * dt * ki * f.x;
+    v.y += 0.5 * dt * ki * f.y;
+    v.z += 0.5 * dt * ki * f.z;
+    p.x += dt * v.x;
+    p.y += dt * v.y;
+    p.z += dt * v.z;
+    S.vel[a] = v;
+    S.pos[a] = p;
+    const float4 r0 = S.ref[a];
+    const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
+    if (dx * dx + dy * dy + dz * dz > S.half_skin2) atomicOr(&S.st->viol[nstep & 1], 1);
+}
+
+// ------------------------------------------------------ layout kernels ---
+
+// Positions in caller order ([n][3], float or double, device) -> internal pos.
+__global__ __launch_bounds__(256) void k_positions_in(Sys S, const void* src, int is_f64)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int c = S.perm[a];
+    double4 p = S.pos[a];
+    if (is_f64) {
+        const double* s = reinterpret_cast<const double*>(src) + 3 * (size_t)c;
+        p.x = s[0];
+        p.y = s[1];
+        p.z = s[2];
+    } else {
+        const float* s = reinterpret_cast<const float*>(src) + 3 * (size_t)c;
+        p.x = s[0];
+        p.y = s[1];
+        p.z = s[2];
+    }
+    S.pos[a] = p;
+}
+
+__global__ __launch_bounds__(256) void k_forces_out(Sys S, double* dst)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int c = S.perm[a];
+    const double4 f = S.frc[a];
+    dst[3 * (size_t)c + 0] = f.x;
+    dst[3 * (size_t)c + 1] = f.y;
+    dst[3 * (size_t)c + 2] = f.z;
+}
+
+__global__ __launch_bounds__(256) void k_energy_out(Sys S, double* dst)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < S.nmol) dst[m] = S.Ecur[m];
+}
+
+__global__ void k_invalidate_lists(Sys S)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        S.st->lists_valid = 0;
+        S.st->viol[0] = 0;
+        S.st->viol[1] = 0;
+    }
+}
+
+// ------------------------------------------------------------ launchers ---
+
+template <int T, int MODE, bool GRAD>
+static hipError_t launch_fused_t(const Sys& S, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_eval_fused<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, S);
+    return hipGetLastError();
+}
+
+template <int T, int MODE, bool GRAD>
+static hipError_t launch_mlp_t(const Sys& S, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_mlp<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s)
+{
+    if (path == 1) {
+#define NNP_FUSED(TT, MM)                                                            \
+    if (T == TT && mode == MM) return grad ? launch_fused_t<TT, MM, true>(S, s)      \
+                                           : launch_fused_t<TT, MM, false>(S, s);
+        NNP_FUSED(4, 0)
+        NNP_FUSED(8, 0)
+        NNP_FUSED(4, 1)
+        NNP_FUSED(8, 1)
+        NNP_FUSED(4, 2)
+        NNP_FUSED(8, 2)
+#undef NNP_FUSED
+        return hipErrorInvalidValue;
+    }
+    const int nb4 = (S.n + 3) / 4;
+    hipLaunchKernelGGL(k_lists, dim3(nb4), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_descriptors, dim3(nb4), dim3(256), 0, s, S);
+    hipError_t e = hipErrorInvalidValue;
+#define NNP_MLP(TT, MM)                                                                                   \
+    if (T == TT && mode == MM) e = grad ? launch_mlp_t<TT, MM, true>(S, s) : launch_mlp_t<TT, MM, false>(S, s);
+    NNP_MLP(8, 0)
+    NNP_MLP(16, 0)
+    NNP_MLP(8, 1)
+    NNP_MLP(16, 1)
+    NNP_MLP(8, 2)
+    NNP_MLP(16, 2)
+#undef NNP_MLP
+    if (e != hipSuccess) return e;
+    if (grad) hipLaunchKernelGGL(k_adjoint, dim3(nb4), dim3(256), 0, s, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + 15) / 16), dim3(256), 0, s, S, dt, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_kickdrift(const Sys& S, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kickdrift, dim3((S.n + 255) / 256), dim3(256), 0, s, S, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_positions_in(const Sys& S, const void* src, int is_f64, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_positions_in, dim3((S.n + 255) / 256), dim3(256), 0, s, S, src, is_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_forces_out, dim3((S.n + 255) / 256), dim3(256), 0, s, S, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_out(const Sys& S, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_out, dim3((S.nmol + 255) / 256), dim3(256), 0, s, S, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_invalidate_lists(const Sys& S, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_invalidate_lists, dim3(1), dim3(64), 0, s, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_descriptors_only(const Sys& S, hipStream_t s)
+{
+    const int nb4 = (S.n + 3) / 4;
+    hipLaunchKernelGGL(k_lists, dim3(nb4), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_descriptors, dim3(nb4), dim3(256), 0, s, S);
+    return hipGetLastError();
+}
+
+}  // namespace nnp
