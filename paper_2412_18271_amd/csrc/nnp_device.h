@@ -41,6 +41,7 @@ struct Env {
     unsigned char ang[kAngMax];     // radial-entry index of neighbours within 3.5 A
     unsigned char smap[kCapMax];    // pair-list slot -> radial entry, or 255
     int nR, nA, nS;                 // radial entries, angular entries, pair-list length
+    int aseg[5];                    // angular entries of element s: [aseg[s], aseg[s+1])
 };
 constexpr unsigned char kNoEntry = 255;
 
@@ -61,51 +62,66 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
 }
 
 // Adds neighbour candidate to the wave's environment (called for every
-// accepted pair-list slot, in slot order, by all 64 lanes together).
-__device__ __forceinline__ void env_append(Env& E, bool valid, int slot, double dx, double dy, double dz,
-                                           int elem, int& nR, int& nA, int& over)
+// accepted pair-list slot, in slot order, by all 64 lanes together).  The
+// relative vector is formed in FP64 from the master positions and rounded to
+// FP32, so the descriptor inputs carry FP32 relative precision at any
+// distance from the origin.
+__device__ __forceinline__ void env_append(Env& E, bool valid, int slot, double dxd, double dyd, double dzd,
+                                           int elem, int& nR, int& nA, int (&nAs)[4], int& over)
 {
     float r = 0.0f;
     bool inR = false, inA = false;
     float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
-        double rd = sqrt(dx * dx + dy * dy + dz * dz);
-        r = (float)rd;
+        const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+        r = sqrtf(dx * dx + dy * dy + dz * dz);
         inR = r < kCutRad;
         inA = r < kCutAng;
-        double inv = 1.0 / rd;
-        g = make_float4((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), r);
+        const float inv = 1.0f / r;
+        g = make_float4(dx * inv, dy * inv, dz * inv, r);
     }
-    unsigned long long mR = __ballot(inR), mA = __ballot(inA);
-    int iR = nR + lanes_below(mR);
-    int iA = nA + lanes_below(mA);
+    const unsigned long long mR = __ballot(inR), mA = __ballot(inA);
+    const int iR = nR + lanes_below(mR);
+    const int iA = nA + lanes_below(mA);
     if (valid) E.smap[slot] = (inR && iR < kRadMax) ? (unsigned char)iR : kNoEntry;
     if (inR && iR < kRadMax) {
         E.geo[iR] = g;
-        float x = r * (1.0f / kCutRad);
+        const float x = r * (1.0f / kCutRad);
         E.fcr[iR] = make_float2(0.5f * cospif(x) + 0.5f, -0.5f * (kPi / kCutRad) * sinpif(x));
         E.info[iR] = (unsigned short)(elem | (slot << 2));
         if (inA && iA < kAngMax) {
-            float y = r * (1.0f / kCutAng);
+            const float y = r * (1.0f / kCutAng);
             E.ang[iA] = (unsigned char)iR;
             E.afc[iA] = make_float2(0.5f * cospif(y) + 0.5f, -0.5f * (kPi / kCutAng) * sinpif(y));
         }
     }
+#pragma unroll
+    for (int e = 0; e < kNumSpecies; ++e) nAs[e] += __popcll(__ballot(inA && elem == e));
     nR += __popcll(mR);
     nA += __popcll(mA);
     over |= (nR > kRadMax) | (nA > kAngMax);
 }
 
-__device__ __forceinline__ void env_finish(const Sys& S, Env& E, int nR, int nA, int nS, int over)
+__device__ __forceinline__ void env_finish(const Sys& S, Env& E, int nR, int nA, const int (&nAs)[4], int nS,
+                                           int over)
 {
     if (lane_id() == 0) {
         E.nR = nR < kRadMax ? nR : kRadMax;
         E.nA = nA < kAngMax ? nA : kAngMax;
         E.nS = nS;
+        int acc = 0;
+        for (int e = 0; e < kNumSpecies; ++e) {
+            E.aseg[e] = acc < E.nA ? acc : E.nA;
+            acc += nAs[e];
+        }
+        E.aseg[kNumSpecies] = E.nA;
         if (over) atomicOr(&S.st->overflow, 1);
-        atomicMax(&S.st->max_ns, nS);
-        atomicMax(&S.st->max_nr, nR);
-        atomicMax(&S.st->max_na, nA);
+        // observability maxima: touch the shared counters only when exceeded
+        // (a plain read first keeps same-address atomics rare)
+        StepState* st = S.st;
+        if (nS > __hip_atomic_load(&st->max_ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&st->max_ns, nS);
+        if (nR > __hip_atomic_load(&st->max_nr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&st->max_nr, nR);
+        if (nA > __hip_atomic_load(&st->max_na, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&st->max_na, nA);
     }
     wave_sync();
 }
@@ -118,6 +134,7 @@ __device__ void build_list_env(const Sys& S, int a, Env& E)
     const double4 pa = S.pos[a];
     const int m = S.mol[a];
     int count = 0, nR = 0, nA = 0, over = 0;
+    int nAs[4] = {0, 0, 0, 0};
     const size_t base = (size_t)a * S.cap;
     for (int e = 0; e < kNumSpecies; ++e) {
         const int2 rg = S.mrange[m * kNumSpecies + e];
@@ -136,7 +153,7 @@ __device__ void build_list_env(const Sys& S, int a, Env& E)
             const int slot = count + lanes_below(mk);
             const bool keep = ok && slot < S.cap;
             if (keep) S.nbr[base + slot] = c;
-            env_append(E, keep, slot, dx, dy, dz, e, nR, nA, over);
+            env_append(E, keep, slot, dx, dy, dz, e, nR, nA, nAs, over);
             count += __popcll(mk);
         }
     }
@@ -146,7 +163,7 @@ __device__ void build_list_env(const Sys& S, int a, Env& E)
         S.ncnt[a] = nS;
         S.ref[a] = make_float4((float)pa.x, (float)pa.y, (float)pa.z, 0.f);
     }
-    env_finish(S, E, nR, nA, nS, over);
+    env_finish(S, E, nR, nA, nAs, nS, over);
 }
 
 // Builds only the pair list (plain path).
@@ -188,6 +205,7 @@ __device__ void load_env(const Sys& S, int a, Env& E)
     const int nS = S.ncnt[a];
     const size_t base = (size_t)a * S.cap;
     int nR = 0, nA = 0, over = 0;
+    int nAs[4] = {0, 0, 0, 0};
     for (int s0 = 0; s0 < nS; s0 += 64) {
         const int s = s0 + lane;
         const bool valid = s < nS;
@@ -200,9 +218,9 @@ __device__ void load_env(const Sys& S, int a, Env& E)
             dz = pj.z - pa.z;
             elem = (int)pj.w;
         }
-        env_append(E, valid, s, dx, dy, dz, elem, nR, nA, over);
+        env_append(E, valid, s, dx, dy, dz, elem, nR, nA, nAs, over);
     }
-    env_finish(S, E, nR, nA, nS, over);
+    env_finish(S, E, nR, nA, nAs, nS, over);
 }
 
 // Radial features G[0..63] of the wave's atom.  Lane (k, q): Gaussian k,
@@ -239,7 +257,7 @@ __device__ void radial_features(const Env& E, float* G)
     }
 }
 
-// Pair q (0 <= q < nA (nA-1)/2) -> angular entries (j < k), enumerated by k then j.
+// Pair q (0 <= q < m (m-1)/2) -> (j < k), enumerated by k then j.
 __device__ __forceinline__ void pair_of(int q, int& j, int& k)
 {
     int kk = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
@@ -249,17 +267,106 @@ __device__ __forceinline__ void pair_of(int q, int& j, int& k)
     j = q - kk * (kk - 1) / 2;
 }
 
-// Angular features added into Gang[0..319] (LDS, zeroed beforehand).  One lane
-// per neighbour pair; the 32 terms of a pair go to the block of its element
-// pair through LDS atomics (one wave per atom, so the order is fixed).
-__device__ void angular_features(const Env& E, float* Gang)
+// Element pairs in feature-block order HH HC HN HO CC CN CO NN NO OO.
+__constant__ static const unsigned char kPairS1[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+__constant__ static const unsigned char kPairS2[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+constexpr int kAccStride = 33;  // padded element-pair block of the angular accumulator
+
+// The pairs (j < k) of angular neighbours of one atom, grouped by element
+// pair p: j in the angular segment of element s1(p), k in that of s2(p).
+// Every group is cut into runs of at most C consecutive pairs, C chosen so
+// that all runs fit in the 64 lanes; a lane owns one run, so every pair it
+// visits belongs to the same feature block.
+struct PairRun {
+    int p;            // element pair of the run, -1 when the lane has none
+    int left;         // pairs in the run
+    int jj, kk;       // position inside the group
+    int lo1, lo2, n2; // segment starts, size of the second segment
+    bool same;        // s1 == s2 (triangular group)
+};
+
+__device__ __forceinline__ PairRun lane_run(const Env& E, int lane)
+{
+    int seg[5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) seg[e] = E.aseg[e];
+    int cnt[10], total = 0;
+#pragma unroll
+    for (int p = 0; p < 10; ++p) {
+        const int s1 = kPairS1[p], s2 = kPairS2[p];
+        const int n1 = seg[s1 + 1] - seg[s1], n2 = seg[s2 + 1] - seg[s2];
+        cnt[p] = s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
+        total += cnt[p];
+    }
+    const int C = total > 48 ? (total + 47) / 48 : 1;  // sum of runs <= 48 + 10
+    PairRun R;
+    R.p = -1;
+    R.left = 0;
+    int first = 0;
+#pragma unroll
+    for (int p = 0; p < 10; ++p) {
+        const int runs = (cnt[p] + C - 1) / C;
+        if (lane >= first && lane < first + runs) {
+            const int q0 = (lane - first) * C;
+            const int s1 = kPairS1[p], s2 = kPairS2[p];
+            R.p = p;
+            R.left = min(C, cnt[p] - q0);
+            R.lo1 = seg[s1];
+            R.lo2 = seg[s2];
+            R.n2 = seg[s2 + 1] - seg[s2];
+            R.same = s1 == s2;
+            if (R.same) {
+                pair_of(q0, R.jj, R.kk);
+            } else {
+                R.jj = q0 / R.n2;
+                R.kk = q0 - R.jj * R.n2;
+            }
+        }
+        first += runs;
+    }
+    return R;
+}
+
+__device__ __forceinline__ void run_pair(const PairRun& R, int& j, int& k)
+{
+    if (R.same) {
+        j = R.lo1 + R.jj;
+        k = R.lo1 + R.kk;
+    } else {
+        j = R.lo1 + R.jj;
+        k = R.lo2 + R.kk;
+    }
+}
+
+__device__ __forceinline__ void run_next(PairRun& R)
+{
+    if (R.same) {
+        if (++R.jj == R.kk) {
+            ++R.kk;
+            R.jj = 0;
+        }
+    } else if (++R.kk == R.n2) {
+        R.kk = 0;
+        ++R.jj;
+    }
+}
+
+// Angular features of the wave's atom, accumulated into acc[10][33] (LDS,
+// zeroed beforehand): each lane sums the 32 terms of its run in registers,
+// then adds them once; element-pair blocks 33 floats apart sit in different
+// banks.  The caller copies acc into G[64 + 32 p + f].
+__device__ void angular_features(const Env& E, float* acc)
 {
     const int lane = lane_id();
-    const int nA = E.nA;
-    const int np = nA * (nA - 1) / 2;
-    for (int q = lane; q < np; q += 64) {
+    PairRun R = lane_run(E, lane);
+    if (R.p < 0) return;
+    float t[32];
+#pragma unroll
+    for (int f = 0; f < 32; ++f) t[f] = 0.f;
+    for (int it = 0; it < R.left; ++it) {
         int j, k;
-        pair_of(q, j, k);
+        run_pair(R, j, k);
+        run_next(R);
         const int ej = E.ang[j], ek = E.ang[k];
         const float4 gj = E.geo[ej], gk = E.geo[ek];
         const float c = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
@@ -273,7 +380,6 @@ __device__ void angular_features(const Env& E, float* Gang)
             const float x = rbar - (0.9f + 0.65f * (float)m);
             B[m] = w * __expf(-kEtaAng * x * x);
         }
-        float* dst = Gang + 32 * pair_type(E.info[ej] & 3, E.info[ek] & 3);
 #pragma unroll
         for (int n = 0; n < kNumSectors; ++n) {
             float u = 1.f + cp * kSecCos[n] + sp * kSecSin[n];
@@ -283,9 +389,19 @@ __device__ void angular_features(const Env& E, float* Gang)
             u = u * u;  // ^16
             u = u * u;  // ^32
 #pragma unroll
-            for (int m = 0; m < kNumShells; ++m) atomicAdd(dst + 8 * m + n, u * B[m]);
+            for (int m = 0; m < kNumShells; ++m) t[8 * m + n] += u * B[m];
         }
     }
+    float* dst = acc + kAccStride * R.p;
+#pragma unroll
+    for (int f = 0; f < 32; ++f) atomicAdd(dst + f, t[f]);
+}
+
+// G[64..383] <- acc[10][33] (wave-cooperative; acc complete).
+__device__ __forceinline__ void angular_store(const float* acc, float* G)
+{
+    const int lane = lane_id();
+    for (int i = lane; i < 320; i += 64) G[64 + i] = acc[kAccStride * (i >> 5) + (i & 31)];
 }
 
 // Adjoint of the descriptors for the wave's atom a: given g = dE_a/dG_a
@@ -317,11 +433,23 @@ __device__ void adjoint_radial(const Env& E, const float* g, float* facc)
 __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
 {
     const int lane = lane_id();
-    const int nA = E.nA;
-    const int np = nA * (nA - 1) / 2;
-    for (int q = lane; q < np; q += 64) {
+    PairRun R = lane_run(E, lane);
+    if (R.p < 0) return;
+    // dE/dG block of the run's element pair, held in registers
+    float gv[32];
+    const float4* gb4 = reinterpret_cast<const float4*>(g + 64 + 32 * R.p);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float4 v = gb4[q];
+        gv[4 * q] = v.x;
+        gv[4 * q + 1] = v.y;
+        gv[4 * q + 2] = v.z;
+        gv[4 * q + 3] = v.w;
+    }
+    for (int it = 0; it < R.left; ++it) {
         int j, k;
-        pair_of(q, j, k);
+        run_pair(R, j, k);
+        run_next(R);
         const int ej = E.ang[j], ek = E.ang[k];
         const float4 gj = E.geo[ej], gk = E.geo[ek];
         const float2 fj = E.afc[j], fk = E.afc[k];
@@ -329,7 +457,6 @@ __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
         const float cp = kCosScale * c;
         const float sp = sqrtf(fmaxf(0.f, 1.f - cp * cp));
         const float rbar = 0.5f * (gj.w + gk.w);
-        const float* gb = g + 64 + 32 * pair_type(E.info[ej] & 3, E.info[ek] & 3);
         // P_n = sum_m g_mn B_m, Q_n = sum_m g_mn dB_m/drbar
         float B[kNumShells], dB[kNumShells];
 #pragma unroll
@@ -345,13 +472,12 @@ __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
             float P = 0.f, Q = 0.f;
 #pragma unroll
             for (int m = 0; m < kNumShells; ++m) {
-                const float gv = gb[8 * m + n];
-                P += gv * B[m];
-                Q += gv * dB[m];
+                P += gv[8 * m + n] * B[m];
+                Q += gv[8 * m + n] * dB[m];
             }
             const float ct = kSecCos[n], st = kSecSin[n];
             const float u = 1.f + cp * ct + sp * st;
-            float u2 = u * u, u4 = u2 * u2, u8 = u4 * u4, u16 = u8 * u8;
+            const float u2 = u * u, u4 = u2 * u2, u8 = u4 * u4, u16 = u8 * u8;
             const float u31 = u16 * u8 * u4 * u2 * u;
             const float A = u31 * u;
             const float dA = 32.f * u31 * (ct - cp * st * inv_sp);

@@ -53,6 +53,7 @@ struct FusedSmem {
     union {
         typename MlpSmemOf<T, MODE>::type m;
         float facc[T * 3 * kRadMax];
+        float acc[T * 10 * kAccStride];  // angular accumulators (descriptor phase)
     } u;
     float E[16];
 };
@@ -76,10 +77,14 @@ __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
             load_env(S, a, E);
     }
     for (int i = tid; i < T * kLdG; i += 64 * T) sm.G[i] = 0.f;
+    for (int i = tid; i < T * 10 * kAccStride; i += 64 * T) sm.u.acc[i] = 0.f;
     __syncthreads();
     if (act) {
+        float* acc = sm.u.acc + wave * 10 * kAccStride;
         radial_features(E, Grow);
-        angular_features(E, Grow + 64);
+        angular_features(E, acc);
+        wave_sync();
+        angular_store(acc, Grow);
     }
     __syncthreads();
     run_mlp<T, MODE, GRAD>(S, tile.z, sm.G, sm.u.m, sm.E, tid);
@@ -110,15 +115,20 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
 {
     __shared__ Env env[4];
     __shared__ __attribute__((aligned(16))) float G[4 * kLdG];
+    __shared__ float acc[4 * 10 * kAccStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int a = blockIdx.x * 4 + wave;
     float* Grow = G + wave * kLdG;
+    float* ac = acc + wave * 10 * kAccStride;
     for (int i = lane; i < kLdG; i += 64) Grow[i] = 0.f;
+    for (int i = lane; i < 10 * kAccStride; i += 64) ac[i] = 0.f;
     if (a < S.n) load_env(S, a, env[wave]);
     __syncthreads();
     if (a < S.n) {
         radial_features(env[wave], Grow);
-        angular_features(env[wave], Grow + 64);
+        angular_features(env[wave], ac);
+        wave_sync();
+        angular_store(ac, Grow);
     }
     __syncthreads();
     if (a < S.n)
