@@ -95,6 +95,24 @@ def run_variant(P, s, dtype, path, steps, warmup, F_ref):
         ctx.close()
 
 
+def copy_calibration(mib):
+    """One device-to-device copy of a known size (the HIP runtime's blit
+    kernel), to scale the FETCH_SIZE / WRITE_SIZE counters of a profile."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    n = int(mib) << 20
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(n)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(n)) == 0
+    assert hip.hipMemset(a, 1, ctypes.c_size_t(n)) == 0
+    for _ in range(3):
+        assert hip.hipMemcpy(b, a, ctypes.c_size_t(n), 3) == 0  # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    log("copy calibration: 3 x %d MiB device-to-device" % mib)
+
+
 def cpu_baseline(s, seconds):
     import oracle
     n = 0
@@ -120,6 +138,8 @@ def main():
     ap.add_argument("--variants", default=",".join("%s:%s" % v for v in VARIANTS))
     ap.add_argument("--profile-only", default=None,
                     help="dtype:path; run only that variant's timed steps (for rocprofv3)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="with --profile-only: also run a device-to-device copy of this size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -138,6 +158,8 @@ def main():
         ctx.step(DT_FS, args.steps, graph=True)
         log("profiled", dtype, path, ctx.stats())
         ctx.close()
+        if args.copy_calibration_mib:
+            copy_calibration(args.copy_calibration_mib)
         return
 
     import oracle

@@ -298,31 +298,40 @@ __device__ __forceinline__ PairRun lane_run(const Env& E, int lane)
         cnt[p] = s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
         total += cnt[p];
     }
-    const int C = total > 48 ? (total + 47) / 48 : 1;  // sum of runs <= 48 + 10
+    // run length C = 2^lc >= total / 48, so the runs fit in 48 + 10 lanes
+    int lc = 0;
+    while ((48 << lc) < total) ++lc;
+    const int C = 1 << lc;
     PairRun R;
     R.p = -1;
     R.left = 0;
-    int first = 0;
+    int first = 0, q0 = 0;
 #pragma unroll
     for (int p = 0; p < 10; ++p) {
-        const int runs = (cnt[p] + C - 1) / C;
+        const int runs = (cnt[p] + C - 1) >> lc;
         if (lane >= first && lane < first + runs) {
-            const int q0 = (lane - first) * C;
             const int s1 = kPairS1[p], s2 = kPairS2[p];
+            q0 = (lane - first) << lc;
             R.p = p;
             R.left = min(C, cnt[p] - q0);
             R.lo1 = seg[s1];
             R.lo2 = seg[s2];
             R.n2 = seg[s2 + 1] - seg[s2];
             R.same = s1 == s2;
-            if (R.same) {
-                pair_of(q0, R.jj, R.kk);
-            } else {
-                R.jj = q0 / R.n2;
-                R.kk = q0 - R.jj * R.n2;
-            }
         }
         first += runs;
+    }
+    if (R.p >= 0) {
+        if (R.same) {
+            pair_of(q0, R.jj, R.kk);
+        } else {
+            // q0 = jj * n2 + kk without an integer division
+            int jj = (int)((float)q0 / (float)R.n2);
+            while (jj * R.n2 > q0) --jj;
+            while ((jj + 1) * R.n2 <= q0) ++jj;
+            R.jj = jj;
+            R.kk = q0 - jj * R.n2;
+        }
     }
     return R;
 }
@@ -435,17 +444,7 @@ __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
     const int lane = lane_id();
     PairRun R = lane_run(E, lane);
     if (R.p < 0) return;
-    // dE/dG block of the run's element pair, held in registers
-    float gv[32];
-    const float4* gb4 = reinterpret_cast<const float4*>(g + 64 + 32 * R.p);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float4 v = gb4[q];
-        gv[4 * q] = v.x;
-        gv[4 * q + 1] = v.y;
-        gv[4 * q + 2] = v.z;
-        gv[4 * q + 3] = v.w;
-    }
+    const float* gb = g + 64 + 32 * R.p;
     for (int it = 0; it < R.left; ++it) {
         int j, k;
         run_pair(R, j, k);
@@ -457,33 +456,41 @@ __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
         const float cp = kCosScale * c;
         const float sp = sqrtf(fmaxf(0.f, 1.f - cp * cp));
         const float rbar = 0.5f * (gj.w + gk.w);
-        // P_n = sum_m g_mn B_m, Q_n = sum_m g_mn dB_m/drbar
-        float B[kNumShells], dB[kNumShells];
+        // P_n = sum_m g_mn B_m, Q_n = sum_m g_mn dB_m/drbar (g rows of the block
+        // read from LDS; lanes of one element pair read the same addresses)
+        float P[kNumSectors], Q[kNumSectors];
+#pragma unroll
+        for (int n = 0; n < kNumSectors; ++n) {
+            P[n] = 0.f;
+            Q[n] = 0.f;
+        }
 #pragma unroll
         for (int m = 0; m < kNumShells; ++m) {
             const float x = rbar - (0.9f + 0.65f * (float)m);
-            B[m] = __expf(-kEtaAng * x * x);
-            dB[m] = -2.f * kEtaAng * x * B[m];
+            const float Bm = __expf(-kEtaAng * x * x);
+            const float dBm = -2.f * kEtaAng * x * Bm;
+            const float4 g0 = *reinterpret_cast<const float4*>(gb + 8 * m);
+            const float4 g1 = *reinterpret_cast<const float4*>(gb + 8 * m + 4);
+            const float gm[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+#pragma unroll
+            for (int n = 0; n < kNumSectors; ++n) {
+                P[n] += gm[n] * Bm;
+                Q[n] += gm[n] * dBm;
+            }
         }
         float Et = 0.f, dEdcp = 0.f, dEdrb = 0.f;
         const float inv_sp = 1.f / sp;
 #pragma unroll
         for (int n = 0; n < kNumSectors; ++n) {
-            float P = 0.f, Q = 0.f;
-#pragma unroll
-            for (int m = 0; m < kNumShells; ++m) {
-                P += gv[8 * m + n] * B[m];
-                Q += gv[8 * m + n] * dB[m];
-            }
             const float ct = kSecCos[n], st = kSecSin[n];
             const float u = 1.f + cp * ct + sp * st;
             const float u2 = u * u, u4 = u2 * u2, u8 = u4 * u4, u16 = u8 * u8;
             const float u31 = u16 * u8 * u4 * u2 * u;
             const float A = u31 * u;
             const float dA = 32.f * u31 * (ct - cp * st * inv_sp);
-            Et += A * P;
-            dEdcp += dA * P;
-            dEdrb += A * Q;
+            Et += A * P[n];
+            dEdcp += dA * P[n];
+            dEdrb += A * Q[n];
         }
         // E_t = w * sum_n A_n P_n with w = 2^-31 fc_j fc_k
         const float pre = kTwoPowM31;
@@ -526,7 +533,7 @@ __device__ void store_slot_forces(const Sys& S, int a, const Env& E, const float
 // ------------------------------------------------------------------------
 
 // LDS row strides (elements) of the activation buffers.
-constexpr int kLdG = kNumFeat + 4;  // fp32 G / dE/dG rows
+constexpr int kLdG = kNumFeat + 8;  // G / dE/dG rows: fp32, or bf16 hi + lo overlaid
 constexpr int kLd1 = kH1 + 8;       // bf16 rows
 constexpr int kLd2 = kH2 + 8;
 constexpr int kLd3 = kH3 + 8;
@@ -617,86 +624,85 @@ __device__ void mlp_f32(const float* __restrict__ w, float* G, MlpF32Smem<T>& sm
     __syncthreads();
 }
 
-// Per-tile LDS of the MFMA network (16 atom columns; unused columns are
-// zero).  Single-pass BF16 keeps the activations as BF16; the split mode
-// keeps them in FP32 and splits every operand into hi + lo BF16 parts.
+// Per-tile LDS of the MFMA network.  Activations are stored as BF16 (and,
+// in the split mode, a second BF16 array with the rounding residual), written
+// once by the producing layer's epilogue and read as B operands by every
+// output tile of the next layer.
 template <int T, bool SPLIT>
 struct MlpMfmaSmem {
-    using AT = typename std::conditional<SPLIT, float, __bf16>::type;
-    static constexpr int LD1 = SPLIT ? kLdF1 : kLd1;
-    static constexpr int LD2 = SPLIT ? kLdF2 : kLd2;
-    static constexpr int LD3 = SPLIT ? kLdF3 : kLd3;
-    AT h1[T * LD1];         // h1, later delta1
-    AT h2[T * LD2];         // h2, later delta2
-    AT h3[T * LD3];         // delta3
-    float d1[T * kLdF1];    // celu'(z1)
-    float d2[T * kLdF2];    // celu'(z2)
-    float ep[8 * 16];       // output-layer partial sums per (m tile, atom)
+    static constexpr int NL = SPLIT ? 2 : 1;  // hi, and lo when split
+    __bf16 h1[NL][T * kLd1];  // h1, later delta1
+    __bf16 h2[NL][T * kLd2];  // h2, later delta2
+    __bf16 h3[NL][T * kLd3];  // delta3
+    float d1[T * kLdF1];      // celu'(z1)
+    float d2[T * kLdF2];      // celu'(z2)
+    float ep[8 * 16];         // output-layer partial sums per (m tile, atom)
 };
 
-__device__ __forceinline__ bf16x8 cvt8(const float4 x0, const float4 x1)
+template <bool SPLIT>
+__device__ __forceinline__ void put_act(__bf16* hi, __bf16* lo, int idx, float v)
 {
-    bf16x8 b;
-    b[0] = (__bf16)x0.x; b[1] = (__bf16)x0.y; b[2] = (__bf16)x0.z; b[3] = (__bf16)x0.w;
-    b[4] = (__bf16)x1.x; b[5] = (__bf16)x1.y; b[6] = (__bf16)x1.z; b[7] = (__bf16)x1.w;
-    return b;
+    const __bf16 h = (__bf16)v;
+    hi[idx] = h;
+    if constexpr (SPLIT) lo[idx] = (__bf16)(v - (float)h);
 }
 
-// hi = bf16(x), lo = bf16(x - hi) for 8 values
-__device__ __forceinline__ void split8(const float* p, bf16x8& hi, bf16x8& lo)
+// G (fp32 [T][kLdG], complete) -> bf16 hi (and lo) rows overlaid on the same
+// LDS: hi at G, lo right after T rows of hi.  Workgroup-wide.
+template <int T, bool SPLIT>
+__device__ __forceinline__ void split_g_inplace(float* G, int tid, int nthr)
 {
-    const float4 x0 = *reinterpret_cast<const float4*>(p);
-    const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
-    hi = cvt8(x0, x1);
-    const float4 r0 = make_float4(x0.x - (float)hi[0], x0.y - (float)hi[1], x0.z - (float)hi[2], x0.w - (float)hi[3]);
-    const float4 r1 = make_float4(x1.x - (float)hi[4], x1.y - (float)hi[5], x1.z - (float)hi[6], x1.w - (float)hi[7]);
-    lo = cvt8(r0, r1);
+    constexpr int PER = (T * kNumFeat + 64 * T - 1) / (64 * T);
+    float v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = tid + q * nthr;
+        v[q] = i < T * kNumFeat ? G[(i / kNumFeat) * kLdG + i % kNumFeat] : 0.f;
+    }
+    __syncthreads();
+    __bf16* hi = reinterpret_cast<__bf16*>(G);
+    __bf16* lo = hi + T * kLdG;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = tid + q * nthr;
+        if (i < T * kNumFeat) put_act<SPLIT>(hi, lo, (i / kNumFeat) * kLdG + i % kNumFeat, v[q]);
+    }
+    __syncthreads();
 }
 
 // One 16 x 16 output tile: rows = outputs of fragment row mt, columns =
 // atoms (columns >= T are zero).  A from pre-swizzled weight fragments
 // (HBM/L2), B from LDS rows.  SPLIT: D = A_hi B_hi + A_hi B_lo + A_lo B_hi
 // (FP32 accumulation).
-template <int T, int KT, bool SPLIT, typename TB>
+template <int T, int KT, bool SPLIT>
 __device__ __forceinline__ floatx4 mfma_tile(const bf16x8* __restrict__ fhi, const bf16x8* __restrict__ flo,
-                                             const TB* act, int ld, int lane)
+                                             const __bf16* bhi, const __bf16* blo, int ld, int lane)
 {
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     const int col = lane & 15, kq = (lane >> 4) * 8;
     const bool live = col < T;
     const bf16x8 zero = {};
+    const int off = (live ? col : 0) * ld + kq;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
         const bf16x8 a = fhi[kt * 64 + lane];
-        const TB* p = act + (live ? col : 0) * ld + kt * 32 + kq;
+        bf16x8 bh = *reinterpret_cast<const bf16x8*>(bhi + off + kt * 32);
+        if (!live) bh = zero;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
         if constexpr (SPLIT) {
-            bf16x8 bh, bl;
-            split8(reinterpret_cast<const float*>(p), bh, bl);
-            if (!live) {
-                bh = zero;
-                bl = zero;
-            }
+            bf16x8 bl = *reinterpret_cast<const bf16x8*>(blo + off + kt * 32);
+            if (!live) bl = zero;
             const bf16x8 al = flo[kt * 64 + lane];
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-        } else {
-            bf16x8 b;
-            if constexpr (std::is_same<TB, float>::value) {
-                const float* q = reinterpret_cast<const float*>(p);
-                b = cvt8(*reinterpret_cast<const float4*>(q), *reinterpret_cast<const float4*>(q + 4));
-            } else {
-                b = *reinterpret_cast<const bf16x8*>(p);
-            }
-            if (!live) b = zero;
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
     }
     return acc;
 }
 
 // MFMA network forward + input gradient for the T atoms of a tile (MFMA
-// columns >= T are zero).  G: [T][kLdG] fp32, replaced by dE/dG when GRAD.
+// columns >= T are zero).  On entry G holds the BF16 (hi, lo) rows made by
+// split_g_inplace; on return (GRAD) it holds dE/dG as fp32 [T][kLdG].
 // fr points at the element's hi fragments; its lo fragments follow after
 // FragLayout::Count fragments.
 template <int T, bool SPLIT, bool GRAD>
@@ -705,22 +711,23 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
 {
     using L = W32Layout;
     using F = FragLayout;
-    using S = MlpMfmaSmem<T, SPLIT>;
-    using AT = typename S::AT;
+    constexpr int LO = SPLIT ? 1 : 0;
     const bf16x8* lo = fr + F::Count * 64;
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
     const int col = lane & 15, rq = (lane >> 4) * 4;
     const bool live = col < T;
+    const __bf16* ghi = reinterpret_cast<const __bf16*>(G);
+    const __bf16* glo = ghi + T * kLdG;
     // layer 1: 160 x 384
     for (int mt = wave; mt < 10; mt += nw) {
         const int f = (F::F1 + mt * 12) * 64;
-        const floatx4 acc = mfma_tile<T, 12, SPLIT>(fr + f, lo + f, G, kLdG, lane);
+        const floatx4 acc = mfma_tile<T, 12, SPLIT>(fr + f, lo + f, ghi, glo, kLdG, lane);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = mt * 16 + rq + i;
-            const float z = acc[i] + w[L::B1 + o];
-            if (live) {
-                sm.h1[col * S::LD1 + o] = (AT)celu_f(z);
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                const float z = acc[i] + w[L::B1 + o];
+                put_act<SPLIT>(sm.h1[0], sm.h1[LO], col * kLd1 + o, celu_f(z));
                 sm.d1[col * kLdF1 + o] = celu_d(z);
             }
         }
@@ -729,13 +736,13 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
     // layer 2: 128 x 160
     for (int mt = wave; mt < 8; mt += nw) {
         const int f = (F::F2 + mt * 5) * 64;
-        const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1, S::LD1, lane);
+        const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1[0], sm.h1[LO], kLd1, lane);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = mt * 16 + rq + i;
-            const float z = acc[i] + w[L::B2 + o];
-            if (live) {
-                sm.h2[col * S::LD2 + o] = (AT)celu_f(z);
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                const float z = acc[i] + w[L::B2 + o];
+                put_act<SPLIT>(sm.h2[0], sm.h2[LO], col * kLd2 + o, celu_f(z));
                 sm.d2[col * kLdF2 + o] = celu_d(z);
             }
         }
@@ -744,7 +751,7 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
     // layer 3: 96 x 128, fused with the output layer and delta3 = celu'(z3) W4
     for (int mt = wave; mt < 6; mt += nw) {
         const int f = (F::F3 + mt * 4) * 64;
-        const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2, S::LD2, lane);
+        const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2[0], sm.h2[LO], kLd2, lane);
         float part = 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -752,7 +759,7 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
             const float z = acc[i] + w[L::B3 + o];
             const float w4 = w[L::W4 + o];
             part += w4 * celu_f(z);
-            if (live) sm.h3[col * S::LD3 + o] = (AT)(celu_d(z) * w4);
+            if (live) put_act<SPLIT>(sm.h3[0], sm.h3[LO], col * kLd3 + o, celu_d(z) * w4);
         }
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
@@ -768,32 +775,37 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
     // delta2 = celu'(z2) * W3^T delta3   (128 x 96)
     for (int mt = wave; mt < 8; mt += nw) {
         const int f = (F::B3 + mt * 3) * 64;
-        const floatx4 acc = mfma_tile<T, 3, SPLIT>(fr + f, lo + f, sm.h3, S::LD3, lane);
+        const floatx4 acc = mfma_tile<T, 3, SPLIT>(fr + f, lo + f, sm.h3[0], sm.h3[LO], kLd3, lane);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = mt * 16 + rq + i;
-            if (live) sm.h2[col * S::LD2 + o] = (AT)(acc[i] * sm.d2[col * kLdF2 + o]);
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                put_act<SPLIT>(sm.h2[0], sm.h2[LO], col * kLd2 + o, acc[i] * sm.d2[col * kLdF2 + o]);
+            }
         }
     }
     __syncthreads();
     // delta1 = celu'(z1) * W2^T delta2   (160 x 128)
     for (int mt = wave; mt < 10; mt += nw) {
         const int f = (F::B2 + mt * 4) * 64;
-        const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2, S::LD2, lane);
+        const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2[0], sm.h2[LO], kLd2, lane);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int o = mt * 16 + rq + i;
-            if (live) sm.h1[col * S::LD1 + o] = (AT)(acc[i] * sm.d1[col * kLdF1 + o]);
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                put_act<SPLIT>(sm.h1[0], sm.h1[LO], col * kLd1 + o, acc[i] * sm.d1[col * kLdF1 + o]);
+            }
         }
     }
     __syncthreads();
-    // dE/dG = W1^T delta1   (384 x 160)
+    // dE/dG = W1^T delta1   (384 x 160), written as fp32 over the (dead) G operand
     for (int mt = wave; mt < 24; mt += nw) {
         const int f = (F::B1 + mt * 5) * 64;
-        const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1, S::LD1, lane);
+        const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1[0], sm.h1[LO], kLd1, lane);
+        if (live) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (live) G[col * kLdG + mt * 16 + rq + i] = acc[i];
+            for (int i = 0; i < 4; ++i) G[col * kLdG + mt * 16 + rq + i] = acc[i];
+        }
     }
     __syncthreads();
 }

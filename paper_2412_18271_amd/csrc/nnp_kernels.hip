@@ -42,6 +42,7 @@ __device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typena
         mlp_f32<T, GRAD>(w, G, sm, E, tid, 64 * T);
     } else {
         const bf16x8* fr = reinterpret_cast<const bf16x8*>(S.wfrag) + (size_t)elem * 2 * FragLayout::Count * 64;
+        split_g_inplace<T, MODE == 2>(G, tid, 64 * T);
         mlp_mfma<T, MODE == 2, GRAD>(w, fr, G, sm, E, tid, 64 * T);
     }
 }
@@ -191,24 +192,58 @@ __device__ __forceinline__ double atomic_read(double* p)
 // mode 0: evaluation only (forces, energies; no integration, step unchanged)
 // mode 1: second half kick (completes a step), step += 1
 // mode 2: as 1, then the first half kick and drift of the next step
-__global__ __launch_bounds__(256) void k_gather_integrate(Sys S, double dt, int mode)
+// One wave per atom (lanes over its pair-list slots), 16 atoms per block.
+constexpr int kGatherAtoms = 16;
+
+__global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, double dt, int mode)
 {
-    __shared__ double sE[16], sK[16];
-    __shared__ int sM[16];
+    __shared__ double sE[kGatherAtoms], sK[kGatherAtoms];
+    __shared__ int sM[kGatherAtoms];
     __shared__ int last;
-    const int tid = threadIdx.x, sub = tid & 15, la = tid >> 4;
-    const int a = blockIdx.x * 16 + la;
+    const int tid = threadIdx.x, lane = tid & 63, la = tid >> 6;
+    const int a = blockIdx.x * kGatherAtoms + la;
     StepState* st = S.st;
     const bool rb = rebuild_due(st, S.rebuild_every);
     const int nstep = st->step;
+    // per-atom integration inputs, issued before the gather so their latency
+    // overlaps it
+    double4 v = make_double4(0, 0, 0, 0), p = make_double4(0, 0, 0, 0);
+    double ki = 0.0, mass = 0.0, e = 0.0;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    int mol = -1;
+    if (lane == 0 && a < S.n) {
+        v = S.vel[a];
+        p = S.pos[a];
+        ki = S.kinv[a];
+        mass = S.mass[a];
+        e = (double)S.Ei[a];
+        r0 = S.ref[a];
+        mol = S.mol[a];
+    }
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (a < S.n) {
+        // a lane holds up to kCapMax / 64 slots; all their loads are issued
+        // together (nbr, rev, own slot force), then the reverse slot forces
+        constexpr int U = kCapMax / 64;
         const int cnt = S.ncnt[a];
         const size_t base = (size_t)a * S.cap;
-        for (int s = sub; s < cnt; s += 16) {
-            const int j = S.nbr[base + s];
-            int r;
-            if (rb) {
+        int jv[U], rv[U];
+        float4 fo[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = lane + 64 * u;
+            jv[u] = -1;
+            if (s < cnt) {
+                jv[u] = S.nbr[base + s];
+                rv[u] = rb ? 0 : S.rev[base + s];
+                fo[u] = S.fslot[base + s];
+            }
+        }
+        if (rb) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jv[u] < 0) continue;
+                const int j = jv[u];
                 const int* lj = S.nbr + (size_t)j * S.cap;
                 int lo = 0, hi = S.ncnt[j] - 1;
                 while (lo < hi) {
@@ -218,37 +253,37 @@ __global__ __launch_bounds__(256) void k_gather_integrate(Sys S, double dt, int 
                     else
                         hi = mid;
                 }
-                r = lo;
-                S.rev[base + s] = r;
-            } else {
-                r = S.rev[base + s];
+                rv[u] = lo;
+                S.rev[base + lane + 64 * u] = lo;
             }
-            const float4 fin = S.fslot[(size_t)j * S.cap + r];
-            const float4 fout = S.fslot[base + s];
-            fx += (double)fin.x - (double)fout.x;
-            fy += (double)fin.y - (double)fout.y;
-            fz += (double)fin.z - (double)fout.z;
+        }
+        float4 fi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (jv[u] >= 0) fi[u] = S.fslot[(size_t)jv[u] * S.cap + rv[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (jv[u] < 0) continue;
+            fx += (double)fi[u].x - (double)fo[u].x;
+            fy += (double)fi[u].y - (double)fo[u].y;
+            fz += (double)fi[u].z - (double)fo[u].z;
         }
     }
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
+    for (int off = 32; off > 0; off >>= 1) {
         fx += __shfl_xor(fx, off);
         fy += __shfl_xor(fy, off);
         fz += __shfl_xor(fz, off);
     }
-    if (sub == 0) {
+    if (lane == 0) {
         if (a < S.n) {
-            double4 v = S.vel[a];
-            double4 p = S.pos[a];
-            const double ki = S.kinv[a];
-            const double e = (double)S.Ei[a];
             S.frc[a] = make_double4(fx, fy, fz, 0.0);
             if (mode >= 1) {
                 v.x += 0.5 * dt * ki * fx;
                 v.y += 0.5 * dt * ki * fy;
                 v.z += 0.5 * dt * ki * fz;
             }
-            const double k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
+            const double k = 0.5 * mass * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
             if (mode == 2) {
                 v.x += 0.5 * dt * ki * fx;
                 v.y += 0.5 * dt * ki * fy;
@@ -257,7 +292,6 @@ __global__ __launch_bounds__(256) void k_gather_integrate(Sys S, double dt, int 
                 p.y += dt * v.y;
                 p.z += dt * v.z;
                 S.pos[a] = p;
-                const float4 r0 = S.ref[a];
                 const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
                 if (dx * dx + dy * dy + dz * dz > S.half_skin2) atomicOr(&st->viol[(nstep + 1) & 1], 1);
             }
@@ -265,7 +299,7 @@ __global__ __launch_bounds__(256) void k_gather_integrate(Sys S, double dt, int 
             if (!isfinite(fx + fy + fz + e)) atomicOr(&st->nonfinite, 1);
             sE[la] = e;
             sK[la] = k;
-            sM[la] = S.mol[a];
+            sM[la] = mol;
         } else {
             sE[la] = 0.0;
             sK[la] = 0.0;
@@ -275,14 +309,14 @@ __global__ __launch_bounds__(256) void k_gather_integrate(Sys S, double dt, int 
     __syncthreads();
     if (tid == 0) {
         int i = 0;
-        while (i < 16) {
+        while (i < kGatherAtoms) {
             const int m = sM[i];
             if (m < 0) {
                 ++i;
                 continue;
             }
             double e = 0.0, k = 0.0;
-            while (i < 16 && sM[i] == m) {
+            while (i < kGatherAtoms && sM[i] == m) {
                 e += sE[i];
                 k += sK[i];
                 ++i;
@@ -451,7 +485,8 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
 
 hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + 15) / 16), dim3(256), 0, s, S, dt, mode);
+    hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + kGatherAtoms - 1) / kGatherAtoms), dim3(64 * kGatherAtoms), 0,
+                       s, S, dt, mode);
     return hipGetLastError();
 }
 
