@@ -29,6 +29,10 @@ using namespace nnp;
 namespace {
 
 constexpr int kShapes[4][2] = {{kH1, kNumFeat}, {kH2, kH1}, {kH3, kH2}, {1, kH3}};
+// Molecules with more atoms than this get a cell grid; smaller ones are
+// scanned completely by every atom when the pair list is rebuilt.
+constexpr int kBruteMax = 4096;
+constexpr long long kMaxCellsPerGrid = 1 << 22;
 constexpr size_t kBlobPerElement = (size_t)kH1 * kNumFeat + kH1 + (size_t)kH2 * kH1 + kH2 + (size_t)kH3 * kH2 + kH3 + kH3 + 1;
 
 struct DevBuf {
@@ -210,6 +214,64 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     std::vector<int> perm_dev(c->perm.begin(), c->perm.end());
     Sys& S = c->S;
     S.ntiles = (int)tiles.size();
+    // cell grids of large molecules, fixed from the first positions
+    std::vector<int> molgrid(c->nmol, -1);
+    std::vector<CellGrid> grids;
+    long long ncells = 0;
+    const double rl = 5.2 + c->skin;
+    for (int m = 0; m < c->nmol; ++m) {
+        const int lo = c->mol_offsets[m], hi = c->mol_offsets[m + 1];
+        if (hi - lo <= kBruteMax) continue;
+        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        for (int i = lo; i < hi; ++i)
+            for (int d = 0; d < 3; ++d) {
+                mn[d] = std::min(mn[d], pos[3 * i + d]);
+                mx[d] = std::max(mx[d], pos[3 * i + d]);
+            }
+        double org[3], span[3];
+        for (int d = 0; d < 3; ++d) {
+            const double L = mx[d] - mn[d];
+            const double margin = std::max(2.0 * rl, 0.5 * L);
+            org[d] = mn[d] - margin;
+            span[d] = L + 2.0 * margin;
+        }
+        double h = rl;
+        int nd[3];
+        for (;;) {
+            long long cells = 1;
+            for (int d = 0; d < 3; ++d) {
+                nd[d] = std::max(1, (int)std::ceil(span[d] / h));
+                cells *= nd[d];
+            }
+            if (cells <= kMaxCellsPerGrid) break;
+            h *= 1.25;
+        }
+        CellGrid G;
+        G.ox = org[0];
+        G.oy = org[1];
+        G.oz = org[2];
+        G.inv_h = 1.0 / h;
+        G.nx = nd[0];
+        G.ny = nd[1];
+        G.nz = nd[2];
+        G.first = (int)ncells;
+        ncells += (long long)nd[0] * nd[1] * nd[2];
+        molgrid[m] = (int)grids.size();
+        grids.push_back(G);
+    }
+    HIP_TRY(c, hipMemcpy((void*)S.molgrid, molgrid.data(), sizeof(int) * c->nmol, hipMemcpyHostToDevice));
+    S.ncells = (int)ncells;
+    if (ncells > 0) {
+        hipError_t e = hipSuccess;
+        S.grids = (const CellGrid*)dev_alloc(c, sizeof(CellGrid) * grids.size(), &e);
+        if (e == hipSuccess) S.cell_count = (int*)dev_alloc(c, sizeof(int) * ncells, &e);
+        if (e == hipSuccess) S.cell_start = (int*)dev_alloc(c, sizeof(int) * (ncells + 1), &e);
+        if (e == hipSuccess) S.cell_fill = (int*)dev_alloc(c, sizeof(int) * ncells, &e);
+        if (e == hipSuccess) S.cell_atoms = (int*)dev_alloc(c, sizeof(int) * n, &e);
+        if (e == hipSuccess) S.cellof = (int*)dev_alloc(c, sizeof(int) * n, &e);
+        if (e != hipSuccess) return hip_fail(c, e, "cell list allocation");
+        HIP_TRY(c, hipMemcpy((void*)S.grids, grids.data(), sizeof(CellGrid) * grids.size(), hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, hipMemcpy(S.pos, p4.data(), sizeof(double4) * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy((void*)S.kinv, kinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy((void*)S.mass, mass.data(), sizeof(double) * n, hipMemcpyHostToDevice));
@@ -511,6 +573,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(Kcur, double*, nm)
     ALLOC(perm, const int*, n)
     ALLOC(stage, double*, 3 * n)
+    ALLOC(molgrid, const int*, nm)
     ALLOC(st, StepState*, 1)
     ALLOC(w32, const float*, (size_t)4 * W32Layout::Stride)
     S.wfrag = dev_alloc(c, (size_t)4 * 2 * FragLayout::Count * 1024, &e);

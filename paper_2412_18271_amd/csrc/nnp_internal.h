@@ -86,8 +86,19 @@ struct StepState {
     long long n_eval, n_rebuild, n_forced;
 };
 
+// Cell grid of one large molecule (cells of edge >= 5.2 + skin; atoms outside
+// the grid are clamped into its boundary cells, which keeps every pair within
+// the list cutoff in adjacent cells).
+struct CellGrid {
+    double ox, oy, oz;  // origin
+    double inv_h;       // 1 / cell edge
+    int nx, ny, nz;     // cells per dimension
+    int first;          // index of the grid's first cell in the global cell arrays
+};
+
 struct Sys {
     int n, nmol, cap, ntiles;
+    int ncells;        // cells over all grids (0: no cell lists)
     int rebuild_every;
     float rlist2;      // (5.2 + skin)^2
     float half_skin2;  // (skin / 2)^2
@@ -119,6 +130,14 @@ struct Sys {
     // plain-path intermediates
     float* G;   // [n][384]
     float* dG;  // [n][384]
+    // cell lists of large molecules
+    const int* molgrid;      // [nmol] grid of the molecule, -1: brute-force candidate scan
+    const CellGrid* grids;
+    int* cell_count;         // [ncells]
+    int* cell_start;         // [ncells + 1]
+    int* cell_fill;          // [ncells]
+    int* cell_atoms;         // [n]
+    int* cellof;             // [n]
 };
 
 // True when the evaluation that reads this state has to rebuild the pair list.

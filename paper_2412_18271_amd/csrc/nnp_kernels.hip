@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
     float* Grow = sm.G + wave * kLdG;
 
     if (act) {
-        if (rb)
+        if (rb && S.molgrid[S.mol[a]] < 0)
             build_list_env(S, a, E);
         else
             load_env(S, a, E);
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_lists(Sys S)
 {
     if (!rebuild_due(S.st, S.rebuild_every)) return;
     const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (a < S.n) build_list(S, a);
+    if (a < S.n && S.molgrid[S.mol[a]] < 0) build_list(S, a);
 }
 
 // Descriptors of all atoms into S.G (internal order).  One wave per atom.
@@ -434,6 +434,165 @@ __global__ void k_invalidate_lists(Sys S)
     }
 }
 
+
+// ------------------------------------------------------------ cell lists ---
+// On rebuild steps of systems with large molecules: counting sort of the
+// atoms of every large molecule into its cell grid, then one wave per atom
+// scans the 27 cells around it and keeps the neighbours within 5.2 + skin,
+// sorted ascending (the order every consumer of the pair list relies on).
+
+__device__ __forceinline__ int clamp_cell(double x, double o, double inv_h, int n)
+{
+    const double f = floor((x - o) * inv_h);
+    return f < 0.0 ? 0 : (f >= (double)n ? n - 1 : (int)f);
+}
+
+__global__ __launch_bounds__(256) void k_cell_zero(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.ncells; i += gridDim.x * blockDim.x) {
+        S.cell_count[i] = 0;
+        S.cell_fill[i] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_count(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int g = S.molgrid[S.mol[a]];
+    if (g < 0) {
+        S.cellof[a] = -1;
+        return;
+    }
+    const CellGrid G = S.grids[g];
+    const double4 p = S.pos[a];
+    const int c = G.first + (clamp_cell(p.z, G.oz, G.inv_h, G.nz) * G.ny + clamp_cell(p.y, G.oy, G.inv_h, G.ny)) * G.nx +
+                  clamp_cell(p.x, G.ox, G.inv_h, G.nx);
+    S.cellof[a] = c;
+    atomicAdd(&S.cell_count[c], 1);
+}
+
+// Exclusive scan of the cell counts (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_cell_scan(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    __shared__ int part[1024];
+    const int t = threadIdx.x, nc = S.ncells;
+    const int per = (nc + 1023) / 1024;
+    const int lo = min(t * per, nc), hi = min(lo + per, nc);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += S.cell_count[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        S.cell_start[i] = run;
+        run += S.cell_count[i];
+    }
+    if (t == 1023) S.cell_start[nc] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_cell_fill(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const int c = S.cellof[a];
+    if (c < 0) return;
+    const int slot = atomicAdd(&S.cell_fill[c], 1);
+    S.cell_atoms[S.cell_start[c] + slot] = a;
+}
+
+// Sorts 256 keys in LDS ascending (one wave, bitonic network).
+__device__ void wave_sort256(int* keys)
+{
+    const int lane = lane_id();
+    for (int k = 2; k <= kCapMax; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < kCapMax; i += 64) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int x = keys[i], y = keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        keys[i] = y;
+                        keys[ixj] = x;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_lists(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    __shared__ int keys[4][kCapMax];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = blockIdx.x * 4 + wave;
+    if (a >= S.n) return;
+    const int g = S.molgrid[S.mol[a]];
+    if (g < 0) return;
+    int* K = keys[wave];
+    const CellGrid G = S.grids[g];
+    const double4 pa = S.pos[a];
+    const int cx = clamp_cell(pa.x, G.ox, G.inv_h, G.nx), cy = clamp_cell(pa.y, G.oy, G.inv_h, G.ny),
+              cz = clamp_cell(pa.z, G.oz, G.inv_h, G.nz);
+    int count = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = cz + dz;
+        if (z < 0 || z >= G.nz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = cy + dy;
+            if (y < 0 || y >= G.ny) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = cx + dx;
+                if (x < 0 || x >= G.nx) continue;
+                const int c = G.first + (z * G.ny + y) * G.nx + x;
+                const int b0 = S.cell_start[c], b1 = S.cell_start[c + 1];
+                for (int i0 = b0; i0 < b1; i0 += 64) {
+                    const int i = i0 + lane;
+                    bool ok = false;
+                    int b = -1;
+                    if (i < b1) {
+                        b = S.cell_atoms[i];
+                        if (b != a) {
+                            const double4 pb = S.pos[b];
+                            const double ex = pb.x - pa.x, ey = pb.y - pa.y, ez = pb.z - pa.z;
+                            ok = ex * ex + ey * ey + ez * ez < (double)S.rlist2;
+                        }
+                    }
+                    const unsigned long long mk = __ballot(ok);
+                    const int slot = count + lanes_below(mk);
+                    if (ok && slot < kCapMax) K[slot] = b;
+                    count += __popcll(mk);
+                }
+            }
+        }
+    }
+    const int kept = count < kCapMax ? count : kCapMax;
+    for (int i = kept + lane; i < kCapMax; i += 64) K[i] = 0x7fffffff;
+    wave_sync();
+    wave_sort256(K);
+    const int nS = count < S.cap ? count : S.cap;
+    const size_t base = (size_t)a * S.cap;
+    for (int i = lane; i < nS; i += 64) S.nbr[base + i] = K[i];
+    if (lane == 0) {
+        S.ncnt[a] = nS;
+        S.ref[a] = make_float4((float)pa.x, (float)pa.y, (float)pa.z, 0.f);
+        if (count > S.cap) atomicOr(&S.st->overflow, 1);
+    }
+}
+
 // ------------------------------------------------------------ launchers ---
 
 template <int T, int MODE, bool GRAD>
@@ -450,8 +609,22 @@ static hipError_t launch_mlp_t(const Sys& S, hipStream_t s)
     return hipGetLastError();
 }
 
+static hipError_t launch_cells(const Sys& S, hipStream_t s)
+{
+    if (S.ncells <= 0) return hipSuccess;
+    const int nb = (S.n + 255) / 256;
+    hipLaunchKernelGGL(k_cell_zero, dim3(min((S.ncells + 255) / 256, 1024)), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, S);
+    hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_cell_lists, dim3((S.n + 3) / 4), dim3(256), 0, s, S);
+    return hipGetLastError();
+}
+
 hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s)
 {
+    hipError_t ec = launch_cells(S, s);
+    if (ec != hipSuccess) return ec;
     if (path == 1) {
 #define NNP_FUSED(TT, MM)                                                            \
     if (T == TT && mode == MM) return grad ? launch_fused_t<TT, MM, true>(S, s)      \
@@ -522,6 +695,8 @@ hipError_t launch_invalidate_lists(const Sys& S, hipStream_t s)
 
 hipError_t launch_descriptors_only(const Sys& S, hipStream_t s)
 {
+    hipError_t ec = launch_cells(S, s);
+    if (ec != hipSuccess) return ec;
     const int nb4 = (S.n + 3) / 4;
     hipLaunchKernelGGL(k_lists, dim3(nb4), dim3(256), 0, s, S);
     hipLaunchKernelGGL(k_descriptors, dim3(nb4), dim3(256), 0, s, S);

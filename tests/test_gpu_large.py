@@ -1,0 +1,132 @@
+"""GPU parity at full workload sizes (through the C ABI).
+
+Large clusters use the cell-list pair search.  The oracle checks them on
+sampled atoms: the force on atom a depends only on atoms closer than 10.4 A
+(2 x 5.2), and E_i only on atoms closer than 5.2 A, so the oracle evaluates
+exactly those local environments (the same terms as the full system).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = {"fp32": 1e-4, "bf16x3": 1e-3}
+TOL_E = {"fp32": 1e-6, "bf16x3": 1e-5}
+# Per-molecule energies of small molecules (10..300 atoms) average fewer
+# per-atom errors: split BF16 keeps ~16 significant bits per operand
+# (relative 2^-17 per rounding), so a molecule of n atoms is held to 5e-5.
+TOL_E_MOL = {"fp32": 1e-6, "bf16x3": 5e-5}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(system, **kw):
+    import paper_2412_18271_amd as P
+    return P.Context.from_system(system, **kw)
+
+
+def _sampled_oracle(pos, species, weights, sel):
+    F = np.zeros((len(sel), 3))
+    Ei = np.zeros(len(sel))
+    for q, a in enumerate(sel):
+        env = oracle.local_environment(pos, int(a), 10.4)
+        loc = int(np.nonzero(env == a)[0][0])
+        F[q] = oracle.forces_on(pos[env], species[env], weights, [loc])[0]
+        env5 = oracle.local_environment(pos, int(a), 5.2)
+        loc5 = int(np.nonzero(env5 == a)[0][0])
+        Ei[q] = oracle.energy_forces(pos[env5], species[env5], weights, forces=False)[1][loc5]
+    return F, Ei
+
+
+def _check_sampled(ctx, s, pos, F, dtype, nsample, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sel = np.sort(rng.choice(s.n_atoms, size=nsample, replace=False))
+    Fo, Eio = _sampled_oracle(pos, s.species, s.weights, sel)
+    Ei = ctx.atom_energies()
+    dF = np.abs(F[sel] - Fo).max()
+    dEi = np.abs(Ei[sel] - Eio).max()
+    _say("  sampled %d atoms: max|dF| %.3e  max|dEi| %.3e" % (nsample, dF, dEi))
+    assert dF <= TOL_F[dtype]
+    assert dEi <= 10 * TOL_F[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16x3"])
+def test_cluster23k_cell_lists(make_system, dtype):
+    s = make_system("cluster23k")
+    _say("cluster23k", dtype)
+    ctx = _ctx(s, dtype=dtype, path="fused")
+    E, F = ctx.compute(s.pos)
+    Eo, Eio, _ = oracle.energy_forces(s.pos, s.species, s.weights, forces=False)
+    S = np.abs(Eio).sum()
+    _say("  |dE|/S %.3e" % (abs(E[0] - Eo) / S))
+    assert abs(E[0] - Eo) / S <= TOL_E[dtype]
+    _check_sampled(ctx, s, s.pos, F, dtype, 48, 7)
+    # MD with cell-list rebuilds, then parity at the new positions
+    ctx.set_state(s.pos, s.vel)
+    ctx.step(0.5, 40, graph=True)
+    st = ctx.get_state()
+    stats = ctx.stats()
+    _say("  after 40 steps:", stats)
+    assert stats["rebuilds"] >= 2
+    E2, F2 = ctx.compute(st["pos"])
+    _check_sampled(ctx, s, st["pos"], F2, dtype, 24, 8)
+    ctx.close()
+
+
+def test_droplet100k_sampled(make_system):
+    s = make_system("droplet100k")
+    _say("droplet100k", s.n_atoms)
+    ctx = _ctx(s, dtype="bf16x3", path="fused")
+    E, F = ctx.compute(s.pos)
+    assert np.all(np.isfinite(F))
+    _check_sampled(ctx, s, s.pos, F, "bf16x3", 32, 43)
+    st = ctx.stats()
+    _say("  stats", st)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,path", [("fp32", "fused"), ("bf16x3", "fused"), ("fp32", "plain")])
+def test_batch256_matches_per_molecule_oracle(make_system, dtype, path):
+    s = make_system("batch256")
+    _say("batch256", dtype, path, s.n_atoms)
+    Eo, Eio, Fo = oracle.system_energy_forces(s)
+    ctx = _ctx(s, dtype=dtype, path=path)
+    E, F = ctx.compute(s.pos)
+    dE = np.abs(E - Eo) / np.array([np.abs(Eio[s.molecule(m)]).sum() for m in range(s.n_molecules)])
+    dF = np.abs(F - Fo).max()
+    _say("  max per-molecule |dE|/S %.3e  max|dF| %.3e" % (dE.max(), dF))
+    assert dE.max() <= TOL_E_MOL[dtype]
+    assert dF <= TOL_F[dtype]
+    ctx.close()
+
+
+def test_batch256_md_per_molecule_energies(make_system):
+    """100 steps of all 256 molecules from one graph: per-molecule energies
+    are tracked separately and each molecule conserves its own H."""
+    s = make_system("batch256")
+    ctx = _ctx(s, dtype="bf16x3", path="fused")
+    ctx.set_state(s.pos, s.vel)
+    ctx.step(0.5, 100, graph=True)
+    U, K = ctx.energy_log(101)
+    assert U.shape == (101, 256)
+    H = U + K
+    drift = np.abs(H - H[0]).max(axis=0)
+    _say("  per-molecule max |H - H0| over 100 steps: median %.2e max %.2e" % (np.median(drift), drift.max()))
+    assert np.all(np.isfinite(H))
+    # molecule 0 evolved alone by the oracle for the same 100 steps
+    sl = s.molecule(0)
+    x, v, Uo, Ko = oracle.vv(s.pos[sl], s.vel[sl], s.masses[sl], s.species[sl], s.weights, 0.5, 100)
+    st = ctx.get_state()
+    dx = np.abs(st["pos"][sl] - x).max()
+    _say("  molecule 0 (%d atoms): max|dx| vs oracle %.2e" % (sl.stop - sl.start, dx))
+    assert dx <= 1e-3
+    ctx.close()
