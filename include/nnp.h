@@ -101,8 +101,12 @@ typedef struct {
                                     <= 256; 0 selects 192 */
     int32_t atoms_per_tile;      /* atoms per workgroup: 4 or 8 (fused path), 8 or 16
                                     (plain path); 0 selects 8 (fused) or 16 (plain) */
-    void* stream;                /* hipStream_t to run on, or NULL for a stream owned by
-                                    the context */
+    void* stream;                /* hipStream_t to run on (see use_stream) */
+    int32_t use_stream;          /* nonzero: run on `stream` even when it is NULL (the null
+                                    stream, e.g. PyTorch's default stream); zero: a NULL
+                                    stream means a stream created and owned by the context.
+                                    Multi-step graphs cannot be captured on the null stream:
+                                    nnp_step then launches its kernels directly. */
 } nnp_params;
 
 /* Creates a context: validates params, sorts atoms into the internal order,
@@ -134,6 +138,23 @@ nnp_status nnp_compute(nnp_context* ctx, const double* pos, const double* box, d
  * result is reported by the next host-synchronising call. */
 nnp_status nnp_compute_device(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy,
                               double* d_forces);
+
+/* Differentiation entry points (the energy-only force-provider contract of the
+ * paper's Methods section, where forces come from differentiating the energy).
+ * Device pointers, caller order, context stream, no host sync.
+ *
+ * nnp_energy_device: energies [n_molecules] (double) at d_pos ([n_atoms][3],
+ *   double if d_pos_is_f64 else float).  keep == 0 (recompute mode): only the
+ *   pair list and the positions stay on the device.  keep != 0 (stored mode):
+ *   the descriptors G and dE/dG ([n_atoms][384] float each) are also kept, at
+ *   2 * 1536 bytes per atom of extra device memory (allocated on first use).
+ * nnp_forces_device: forces [n_atoms][3] (double) at the positions of the
+ *   last nnp_energy_device call: from the kept dE/dG through the adjoint
+ *   alone (stored mode), or by recomputing descriptors, network forward and
+ *   backward and the adjoint (recompute mode).  NNP_ERR_STATE without a
+ *   preceding nnp_energy_device call. */
+nnp_status nnp_energy_device(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy, int keep);
+nnp_status nnp_forces_device(nnp_context* ctx, double* d_forces);
 
 /* Sets positions and velocities (host [n_atoms][3] double, caller order;
  * either may be NULL to keep the current value). Forces are recomputed lazily. */

@@ -19,7 +19,8 @@ DTYPES = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
 PATHS = {"plain": 0, "fused": 1}
 
 #: Every function the header declares.
-EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nnp_set_state",
+EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nnp_energy_device",
+           "nnp_forces_device", "nnp_set_state",
            "nnp_get_state", "nnp_step", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
            "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels",
            "nnp_last_error", "nnp_status_string")
@@ -41,6 +42,7 @@ class Params(ctypes.Structure):
         ("max_neighbors", ctypes.c_int32),
         ("atoms_per_tile", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("use_stream", ctypes.c_int32),
     ]
 
 
@@ -71,6 +73,8 @@ def load():
         "nnp_destroy": (None, [vp]),
         "nnp_compute": (st, [vp, P(d), P(d), P(d), P(d)]),
         "nnp_compute_device": (st, [vp, vp, ctypes.c_int, vp, vp]),
+        "nnp_energy_device": (st, [vp, vp, ctypes.c_int, vp, ctypes.c_int]),
+        "nnp_forces_device": (st, [vp, vp]),
         "nnp_set_state": (st, [vp, P(d), P(d)]),
         "nnp_get_state": (st, [vp, P(d), P(d), P(d), P(d), P(d)]),
         "nnp_step": (st, [vp, d, i32, i32]),

@@ -19,8 +19,8 @@ class Context:
     """Wraps nnp_create .. nnp_destroy.
 
     species, masses, weights and mol_offsets are copied by the library at
-    creation.  ``stream`` is a raw hipStream_t (int) or None for a stream the
-    context owns.
+    creation.  ``stream`` is a raw hipStream_t (int; 0 is the null stream)
+    or None for a stream the context owns.
     """
 
     def __init__(self, species, masses, weights, mol_offsets=None, dtype: str = "fp32",
@@ -53,7 +53,8 @@ class Context:
         p.skin = float(skin)
         p.max_neighbors = int(max_neighbors)
         p.atoms_per_tile = int(atoms_per_tile)
-        p.stream = stream
+        p.stream = stream if stream else None
+        p.use_stream = 0 if stream is None else 1
         h = ctypes.c_void_p()
         s = self._lib.nnp_create(ctypes.byref(p), ctypes.byref(h))
         if s != _lib.NNP_OK:
@@ -106,6 +107,15 @@ class Context:
         self._check(self._lib.nnp_compute_device(self._h, ctypes.c_void_p(d_pos), int(pos_is_f64),
                                                  ctypes.c_void_p(d_energy),
                                                  ctypes.c_void_p(d_forces) if d_forces else None))
+
+    def energy_device(self, d_pos: int, pos_is_f64: bool, d_energy: int, keep: bool):
+        """Energy only, on the context stream (no sync); keep=True stores G
+        and dE/dG for a following forces_device()."""
+        self._check(self._lib.nnp_energy_device(self._h, ctypes.c_void_p(d_pos), int(pos_is_f64),
+                                                ctypes.c_void_p(d_energy), 1 if keep else 0))
+
+    def forces_device(self, d_forces: int):
+        self._check(self._lib.nnp_forces_device(self._h, ctypes.c_void_p(d_forces)))
 
     def set_state(self, pos=None, vel=None):
         p = self._pos(pos) if pos is not None else None

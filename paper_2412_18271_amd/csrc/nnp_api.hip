@@ -67,6 +67,7 @@ struct nnp_context {
     Sys S{};
     bool forces_current = false;
     bool kick_pending = false;  // previous block ended after a completed step (mode 1)
+    int diff_state = 0;         // 0: none, 1: energy evaluated (recompute), 2: energy + kept G, dE/dG
     std::map<std::tuple<int, double, int, int, int>, hipGraphExec_t> graphs;
     // pinned staging
     double* h_stage = nullptr;
@@ -528,7 +529,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
         for (int i = c->mol_offsets[m]; i < c->mol_offsets[m + 1]; ++i) c->mol_of[i] = m;
 
     hipError_t e = hipSuccess;
-    if (p->stream) {
+    if (p->stream || p->use_stream) {
         c->stream = (hipStream_t)p->stream;
     } else {
         e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
@@ -614,9 +615,58 @@ void nnp_destroy(nnp_context* c)
     delete c;
 }
 
+nnp_status nnp_energy_device(nnp_context* c, const void* d_pos, int is_f64, double* d_energy, int keep)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!d_pos || !d_energy) return fail(c, NNP_ERR_ARG, "d_pos and d_energy are required");
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions once with nnp_set_state or nnp_compute first");
+    if (keep && (!c->S.G || !c->S.dG)) {
+        hipError_t e = hipSuccess;
+        c->S.G = (float*)dev_alloc(c, sizeof(float) * (size_t)c->n * kNumFeat, &e);
+        if (e == hipSuccess) c->S.dG = (float*)dev_alloc(c, sizeof(float) * (size_t)c->n * kNumFeat, &e);
+        if (e != hipSuccess) return hip_fail(c, e, "stored-mode buffers");
+    }
+    HIP_TRY(c, launch_positions_in(c->S, d_pos, is_f64 ? 1 : 0, c->stream));
+    HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
+    if (keep) {
+        // plain-path kernels keep G and dE/dG; the pair list stays marked for
+        // rebuild so the adjoint's gather records the reverse slots
+        HIP_TRY(c, launch_store_forward(c->S, mode_of(c), c->T, c->stream));
+        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream, false));
+    } else {
+        HIP_TRY(c, enqueue_eval(c, false));
+        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream, false));
+    }
+    HIP_TRY(c, launch_energy_out(c->S, d_energy, c->stream));
+    c->diff_state = keep ? 2 : 1;
+    c->forces_current = false;
+    c->kick_pending = false;
+    return NNP_OK;
+}
+
+nnp_status nnp_forces_device(nnp_context* c, double* d_forces)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!d_forces) return fail(c, NNP_ERR_ARG, "d_forces is required");
+    if (c->diff_state == 0) return fail(c, NNP_ERR_STATE, "call nnp_energy_device first");
+    if (c->diff_state == 2) {
+        // stored mode: the pair list and reverse slots of the forward are
+        // current; the adjoint reads the kept dE/dG
+        HIP_TRY(c, launch_adjoint(c->S, c->stream));
+    } else {
+        HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
+        HIP_TRY(c, enqueue_eval(c, true));
+    }
+    HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream, true));
+    HIP_TRY(c, launch_forces_out(c->S, d_forces, c->stream));
+    c->forces_current = true;
+    return NNP_OK;
+}
+
 nnp_status nnp_set_state(nnp_context* c, const double* pos, const double* vel)
 {
     if (!c) return NNP_ERR_ARG;
+    c->diff_state = 0;
     if (vel)
         for (int i = 0; i < 3 * c->n; ++i)
             if (!std::isfinite(vel[i])) return fail(c, NNP_ERR_NONFINITE, "non-finite velocity component");
@@ -646,6 +696,7 @@ nnp_status nnp_set_state(nnp_context* c, const double* pos, const double* vel)
 nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, double* energy, double* forces)
 {
     if (!c) return NNP_ERR_ARG;
+    c->diff_state = 0;
     if (box) return fail(c, NNP_ERR_UNSUPPORTED, "periodic boxes are not supported (gas phase only)");
     if (!pos || !energy) return fail(c, NNP_ERR_ARG, "pos and energy are required");
     nnp_status s = upload_positions(c, pos);
@@ -676,6 +727,7 @@ nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, dou
 nnp_status nnp_compute_device(nnp_context* c, const void* d_pos, int is_f64, double* d_energy, double* d_forces)
 {
     if (!c) return NNP_ERR_ARG;
+    c->diff_state = 0;
     if (!d_pos || !d_energy) return fail(c, NNP_ERR_ARG, "d_pos and d_energy are required");
     if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions once with nnp_set_state or nnp_compute first");
     HIP_TRY(c, launch_positions_in(c->S, d_pos, is_f64 ? 1 : 0, c->stream));
@@ -697,6 +749,7 @@ nnp_status nnp_compute_device(nnp_context* c, const void* d_pos, int is_f64, dou
 nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph)
 {
     if (!c) return NNP_ERR_ARG;
+    c->diff_state = 0;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, NNP_ERR_ARG, "dt must be finite and > 0");
     if (nsteps < 0) return fail(c, NNP_ERR_ARG, "n_steps must be >= 0");
     if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before stepping");
@@ -705,7 +758,7 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         HIP_TRY(c, enqueue_compute(c, true));
         c->forces_current = true;
     }
-    if (!use_graph) {
+    if (!use_graph || c->stream == nullptr) {
         HIP_TRY(c, enqueue_steps(c, dt, nsteps, true));
         c->kick_pending = true;
         return NNP_OK;

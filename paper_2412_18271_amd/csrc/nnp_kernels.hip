@@ -195,7 +195,7 @@ __device__ __forceinline__ double atomic_read(double* p)
 // One wave per atom (lanes over its pair-list slots), 16 atoms per block.
 constexpr int kGatherAtoms = 16;
 
-__global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, double dt, int mode)
+__global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, double dt, int mode, int forces)
 {
     __shared__ double sE[kGatherAtoms], sK[kGatherAtoms];
     __shared__ int sM[kGatherAtoms];
@@ -221,7 +221,9 @@ __global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, d
         mol = S.mol[a];
     }
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (a < S.n) {
+    // without forces the slot loop still runs on rebuild steps: the reverse
+    // slot indices of the new pair list are recorded here
+    if (a < S.n && (forces || rb)) {
         // a lane holds up to kCapMax / 64 slots; all their loads are issued
         // together (nbr, rev, own slot force), then the reverse slot forces
         constexpr int U = kCapMax / 64;
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, d
     }
     if (lane == 0) {
         if (a < S.n) {
-            S.frc[a] = make_double4(fx, fy, fz, 0.0);
+            if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
             if (mode >= 1) {
                 v.x += 0.5 * dt * ki * fx;
                 v.y += 0.5 * dt * ki * fy;
@@ -609,6 +611,8 @@ static hipError_t launch_mlp_t(const Sys& S, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_descriptors_only(const Sys& S, hipStream_t s);
+
 static hipError_t launch_cells(const Sys& S, hipStream_t s)
 {
     if (S.ncells <= 0) return hipSuccess;
@@ -650,16 +654,36 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
     NNP_MLP(16, 1)
     NNP_MLP(8, 2)
     NNP_MLP(16, 2)
-#undef NNP_MLP
     if (e != hipSuccess) return e;
     if (grad) hipLaunchKernelGGL(k_adjoint, dim3(nb4), dim3(256), 0, s, S);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s)
+hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces)
 {
     hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + kGatherAtoms - 1) / kGatherAtoms), dim3(64 * kGatherAtoms), 0,
-                       s, S, dt, mode);
+                       s, S, dt, mode, forces ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_forward(const Sys& S, int mode, int T, hipStream_t s)
+{
+    const bool grad = true;
+    hipError_t e = launch_descriptors_only(S, s);
+    if (e != hipSuccess) return e;
+    e = hipErrorInvalidValue;
+    NNP_MLP(8, 0)
+    NNP_MLP(16, 0)
+    NNP_MLP(8, 1)
+    NNP_MLP(16, 1)
+    NNP_MLP(8, 2)
+    NNP_MLP(16, 2)
+    return e;
+}
+
+hipError_t launch_adjoint(const Sys& S, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adjoint, dim3((S.n + 3) / 4), dim3(256), 0, s, S);
     return hipGetLastError();
 }
 

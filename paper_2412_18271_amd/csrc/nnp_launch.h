@@ -10,7 +10,11 @@ namespace nnp {
 // 1 = BF16 MFMA, 2 = split BF16 MFMA (hi/lo operands, three products).
 hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s);
 // Force gather + velocity Verlet + energies + step-state update (see kernel).
-hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s);
+hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces = true);
+// Stored-intermediates forward (pair list, descriptors -> S.G, network with
+// dE/dG -> S.dG) and the adjoint from S.dG (plain-path kernels, tile size T).
+hipError_t launch_store_forward(const Sys& S, int mode, int T, hipStream_t s);
+hipError_t launch_adjoint(const Sys& S, hipStream_t s);
 hipError_t launch_kickdrift(const Sys& S, double dt, hipStream_t s);
 hipError_t launch_positions_in(const Sys& S, const void* src, int is_f64, hipStream_t s);
 hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s);

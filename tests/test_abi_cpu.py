@@ -58,6 +58,7 @@ def _params(P, s, **kw):
     p.skin = 1.0
     p.max_neighbors = 0
     p.atoms_per_tile = 0
+    p.use_stream = 0
     for k, v in kw.items():
         setattr(p, k, v)
     return p, keep
