@@ -68,7 +68,9 @@ typedef enum { NNP_RETURN_ENERGY = 1, NNP_RETURN_ENERGY_FORCES = 3 } nnp_return;
  * every mode; energy reduction and integration are FP64.
  *   NNP_MLP_FP32        FP32 FMA on the vector ALUs;
  *   NNP_MLP_BF16        BF16 MFMA, FP32 accumulation, one product per GEMM;
- *   NNP_MLP_FP8         OCP E4M3 MFMA with per-layer scales (not available);
+ *   NNP_MLP_FP8         OCP FP8 E4M3 MFMA, FP32 accumulation: weights scaled per
+ *                       matrix by 448 / amax|W| (static), every other operand per
+ *                       tile and layer by 448 / amax of the tile (no saturation);
  *   NNP_MLP_BF16_SPLIT  BF16 MFMA on split operands: each FP32 weight and
  *                       activation x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
  *                       hi*hi + hi*lo + lo*hi, FP32 accumulation (three MFMAs). */
@@ -213,6 +215,11 @@ nnp_status nnp_autotune(nnp_context* ctx, const char* cache_path);
  * energy kernel alone.  ms[0] and ms[1] receive the average milliseconds per
  * launch of each.  Used by the benchmark's roofline report.  Synchronises. */
 nnp_status nnp_time_kernels(nnp_context* ctx, int32_t reps, double* ms);
+
+/* E4M3 encodings of x[n]: host_out by the library's host encoder (used for
+ * the weights), device_out by the device conversion instruction (used for
+ * activations); either may be NULL.  A format check, no context needed. */
+nnp_status nnp_debug_fp8_encode(const float* x, int32_t n, uint8_t* device_out, uint8_t* host_out);
 
 /* Message for the most recent failure on this context ("" if none). */
 const char* nnp_last_error(const nnp_context* ctx);

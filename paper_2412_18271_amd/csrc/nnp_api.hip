@@ -309,8 +309,36 @@ nnp_status retile(nnp_context* c, int T)
     return NNP_OK;
 }
 
-void build_weights(const std::vector<float>& blob, std::vector<float>& w32, std::vector<uint16_t>& frag)
+// OCP FP8 E4M3 (bias 7, no infinities, 0x7f/0xff NaN, largest finite 448):
+// round to nearest even, values beyond 448 saturate to 448.
+uint8_t e4m3_encode(float x)
 {
+    const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+    const float a = std::fabs(x);
+    if (std::isnan(a)) return 0x7f;
+    if (a >= 448.0f) return sign | 0x7e;
+    if (a < std::ldexp(1.0f, -6)) {  // subnormal: m * 2^-9, m = 0..7 (8 is the smallest normal)
+        const int m = (int)std::nearbyint(a * 512.0f);
+        return sign | (uint8_t)m;
+    }
+    int e2;
+    std::frexp(a, &e2);
+    int E = e2 - 1;  // a = (1 + m/8) 2^E
+    int m = (int)std::nearbyint((a / std::ldexp(1.0f, E) - 1.0f) * 8.0f);
+    if (m == 8) {
+        m = 0;
+        ++E;
+    }
+    int code = ((E + 7) << 3) | m;
+    if (code > 0x7e) code = 0x7e;
+    return sign | (uint8_t)code;
+}
+
+void build_weights(const std::vector<float>& blob, std::vector<float>& w32, std::vector<uint16_t>& frag,
+                   std::vector<uint8_t>& frag8, std::vector<float>& wscale8)
+{
+    frag8.assign((size_t)4 * FragLayout::Count * 512, 0);
+    wscale8.assign(4 * 6, 1.0f);
     w32.assign((size_t)4 * W32Layout::Stride, 0.f);
     frag.assign((size_t)4 * 2 * FragLayout::Count * 64 * 8, 0);
     auto bf16 = [](float x) -> uint16_t {  // round to nearest even
@@ -378,12 +406,40 @@ void build_weights(const std::vector<float>& blob, std::vector<float>& w32, std:
         put_frag(FragLayout::B3, kH2, kH3, true, W[2], kH2);
         put_frag(FragLayout::B2, kH1, kH2, true, W[1], kH1);
         put_frag(FragLayout::B1, kNumFeat, kH1, true, W[0], kNumFeat);
+        // E4M3 fragments, one static scale 448 / amax|W| per matrix
+        uint8_t* f8 = frag8.data() + (size_t)e * FragLayout::Count * 512;
+        auto put_frag8 = [&](int layer, int base, int M, int K, bool transpose, const float* Wm, int ldw, int nW) {
+            float amax = 0.f;
+            for (int i = 0; i < nW; ++i) amax = std::max(amax, std::fabs(Wm[i]));
+            const float sc = amax > 0.f ? 448.0f / amax : 1.0f;
+            wscale8[e * 6 + layer] = 1.0f / sc;
+            const int KT = K / 32;
+            for (int mt = 0; mt < M / 16; ++mt)
+                for (int kt = 0; kt < KT; ++kt)
+                    for (int l = 0; l < 64; ++l)
+                        for (int i = 0; i < 8; ++i) {
+                            const int r = 16 * mt + (l % 16), k = 32 * kt + 8 * (l / 16) + i;
+                            const float v = transpose ? Wm[(size_t)k * ldw + r] : Wm[(size_t)r * ldw + k];
+                            f8[((size_t)(base + mt * KT + kt) * 64 + l) * 8 + i] = e4m3_encode(v * sc);
+                        }
+        };
+        put_frag8(0, FragLayout::F1, kH1, kNumFeat, false, W[0], kNumFeat, kH1 * kNumFeat);
+        put_frag8(1, FragLayout::F2, kH2, kH1, false, W[1], kH1, kH2 * kH1);
+        put_frag8(2, FragLayout::F3, kH3, kH2, false, W[2], kH2, kH3 * kH2);
+        put_frag8(3, FragLayout::B3, kH2, kH3, true, W[2], kH2, kH3 * kH2);
+        put_frag8(4, FragLayout::B2, kH1, kH2, true, W[1], kH1, kH2 * kH1);
+        put_frag8(5, FragLayout::B1, kNumFeat, kH1, true, W[0], kNumFeat, kH1 * kNumFeat);
     }
 }
 
 int mode_of(const nnp_context* c)
 {
-    return c->dtype == NNP_MLP_BF16 ? 1 : c->dtype == NNP_MLP_BF16_SPLIT ? 2 : 0;
+    switch (c->dtype) {
+        case NNP_MLP_BF16: return 1;
+        case NNP_MLP_BF16_SPLIT: return 2;
+        case NNP_MLP_FP8: return 3;
+        default: return 0;
+    }
 }
 
 hipError_t enqueue_eval(nnp_context* c, bool grad)
@@ -483,8 +539,8 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
     if (p->weights_count != 4 * kBlobPerElement) return msg = "weights_count must be 4 * 94689", NNP_ERR_ARG;
     for (size_t i = 0; i < p->weights_count; ++i)
         if (!std::isfinite(p->weights[i])) return msg = "non-finite weight", NNP_ERR_NONFINITE;
-    if (p->mlp_dtype == NNP_MLP_FP8) return msg = "FP8 network GEMMs are not available", NNP_ERR_UNSUPPORTED;
-    if (p->mlp_dtype != NNP_MLP_FP32 && p->mlp_dtype != NNP_MLP_BF16 && p->mlp_dtype != NNP_MLP_BF16_SPLIT)
+    if (p->mlp_dtype != NNP_MLP_FP32 && p->mlp_dtype != NNP_MLP_BF16 && p->mlp_dtype != NNP_MLP_BF16_SPLIT &&
+        p->mlp_dtype != NNP_MLP_FP8)
         return msg = "unknown mlp_dtype", NNP_ERR_ARG;
     if (p->path != NNP_PATH_PLAIN && p->path != NNP_PATH_FUSED) return msg = "unknown path", NNP_ERR_ARG;
     if (p->rebuild_every < 1) return msg = "rebuild_every must be >= 1", NNP_ERR_ARG;
@@ -579,18 +635,26 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(w32, const float*, (size_t)4 * W32Layout::Stride)
     S.wfrag = dev_alloc(c, (size_t)4 * 2 * FragLayout::Count * 1024, &e);
     if (e != hipSuccess) goto oom;
+    S.wfrag8 = dev_alloc(c, (size_t)4 * FragLayout::Count * 512, &e);
+    if (e != hipSuccess) goto oom;
+    ALLOC(wscale8, const float*, 4 * 6)
     if (c->path == NNP_PATH_PLAIN) {
         ALLOC(G, float*, n * kNumFeat)
         ALLOC(dG, float*, n * kNumFeat)
     }
 #undef ALLOC
     {
-        std::vector<float> w32;
+        std::vector<float> w32, ws8;
         std::vector<uint16_t> frag;
-        build_weights(c->weights, w32, frag);
+        std::vector<uint8_t> frag8;
+        build_weights(c->weights, w32, frag, frag8, ws8);
         e = hipMemcpy((void*)S.w32, w32.data(), sizeof(float) * w32.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy((void*)S.wfrag, frag.data(), sizeof(uint16_t) * frag.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void*)S.wfrag8, frag8.data(), frag8.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((void*)S.wscale8, ws8.data(), sizeof(float) * ws8.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) goto oom;
     }
@@ -920,6 +984,27 @@ nnp_status nnp_device_bytes(nnp_context* c, int64_t* bytes)
     for (auto& x : c->bufs) b += (int64_t)x.bytes;
     *bytes = b;
     return NNP_OK;
+}
+
+nnp_status nnp_debug_fp8_encode(const float* x, int32_t n, uint8_t* device_out, uint8_t* host_out)
+{
+    if (!x || n <= 0 || (!device_out && !host_out)) return NNP_ERR_ARG;
+    if (host_out)
+        for (int i = 0; i < n; ++i) host_out[i] = e4m3_encode(x[i]);
+    if (!device_out) return NNP_OK;
+    float* dx = nullptr;
+    uint8_t* dq = nullptr;
+    if (hipMalloc(&dx, sizeof(float) * n) != hipSuccess) return NNP_ERR_OOM;
+    if (hipMalloc(&dq, n) != hipSuccess) {
+        (void)hipFree(dx);
+        return NNP_ERR_OOM;
+    }
+    hipError_t e = hipMemcpy(dx, x, sizeof(float) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_fp8_encode(dx, n, dq, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(device_out, dq, n, hipMemcpyDeviceToHost);
+    (void)hipFree(dx);
+    (void)hipFree(dq);
+    return e == hipSuccess ? NNP_OK : NNP_ERR_HIP;
 }
 
 nnp_status nnp_time_kernels(nnp_context* c, int32_t reps, double* ms)

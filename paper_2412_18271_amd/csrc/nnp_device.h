@@ -810,4 +810,170 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
     __syncthreads();
 }
 
+// ------------------------------------------------------------------------
+// FP8 (OCP E4M3, max 448) network: weights carry a static per-layer scale
+// 448 / amax|W|; every B operand (descriptors, activations, deltas) is
+// quantized per tile and layer with 448 / amax of that tile, so nothing
+// saturates; FP32 accumulation, dequantised in the epilogue.
+// ------------------------------------------------------------------------
+constexpr int kLdQ = kNumFeat + 16;  // bytes per quantized row
+
+template <int T>
+struct MlpFp8Smem {
+    float a1[T * kLdF1];         // h1, later delta1 (fp32)
+    float a2[T * kLdF2];         // h2, later delta2
+    float a3[T * kLdF3];         // delta3
+    float d1[T * kLdF1];         // celu'(z1)
+    float d2[T * kLdF2];         // celu'(z2)
+    unsigned char q[T * kLdQ];   // quantized B operand of the current layer
+    float ep[8 * 16];
+    unsigned amax;
+};
+
+// src [T][ld] (first K columns) -> E4M3 rows of q scaled by 448 / amax;
+// returns the inverse scale.  Workgroup-wide.
+template <int T>
+__device__ float quantize_tile(const float* src, int ld, int K, unsigned char* q, unsigned* amax, int tid, int nthr)
+{
+    if (tid == 0) *amax = 0u;
+    __syncthreads();
+    float m = 0.f;
+    for (int i = tid; i < T * K; i += nthr) m = fmaxf(m, fabsf(src[(i / K) * ld + i % K]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((tid & 63) == 0) atomicMax(amax, __float_as_uint(m));
+    __syncthreads();
+    const float am = __uint_as_float(*amax);
+    const float sc = am > 0.f ? 448.f / am : 1.f;
+    for (int i4 = tid; i4 < T * K / 4; i4 += nthr) {
+        const int t = (4 * i4) / K, k = (4 * i4) % K;
+        const float4 v = *reinterpret_cast<const float4*>(src + t * ld + k);
+        int wd = __builtin_amdgcn_cvt_pk_fp8_f32(v.x * sc, v.y * sc, 0, false);
+        wd = __builtin_amdgcn_cvt_pk_fp8_f32(v.z * sc, v.w * sc, wd, true);
+        *reinterpret_cast<int*>(q + t * kLdQ + k) = wd;
+    }
+    __syncthreads();
+    return 1.f / sc;
+}
+
+template <int T, int KT>
+__device__ __forceinline__ floatx4 mfma_tile_fp8(const long* __restrict__ frag, const unsigned char* q, int lane)
+{
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int col = lane & 15, kq = (lane >> 4) * 8;
+    const bool live = col < T;
+    const unsigned char* row = q + (live ? col : 0) * kLdQ + kq;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+        const long a = frag[kt * 64 + lane];
+        long b = *reinterpret_cast<const long*>(row + kt * 32);
+        if (!live) b = 0;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// FP8 network forward + input gradient.  G: fp32 [T][kLdG], replaced by
+// dE/dG when GRAD.  ws: inverse weight scales of layers F1 F2 F3 B3 B2 B1.
+template <int T, bool GRAD>
+__device__ void mlp_fp8(const float* __restrict__ w, const long* __restrict__ fr, const float* __restrict__ ws,
+                        float* G, MlpFp8Smem<T>& sm, float* E, int tid, int nthr)
+{
+    using L = W32Layout;
+    using F = FragLayout;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    const int col = lane & 15, rq = (lane >> 4) * 4;
+    const bool live = col < T;
+    // layer 1: 160 x 384
+    float dq = quantize_tile<T>(G, kLdG, kNumFeat, sm.q, &sm.amax, tid, nthr) * ws[0];
+    for (int mt = wave; mt < 10; mt += nw) {
+        const floatx4 acc = mfma_tile_fp8<T, 12>(fr + (F::F1 + mt * 12) * 64, sm.q, lane);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                const float z = acc[i] * dq + w[L::B1 + o];
+                sm.a1[col * kLdF1 + o] = celu_f(z);
+                sm.d1[col * kLdF1 + o] = celu_d(z);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2: 128 x 160
+    dq = quantize_tile<T>(sm.a1, kLdF1, kH1, sm.q, &sm.amax, tid, nthr) * ws[1];
+    for (int mt = wave; mt < 8; mt += nw) {
+        const floatx4 acc = mfma_tile_fp8<T, 5>(fr + (F::F2 + mt * 5) * 64, sm.q, lane);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                const float z = acc[i] * dq + w[L::B2 + o];
+                sm.a2[col * kLdF2 + o] = celu_f(z);
+                sm.d2[col * kLdF2 + o] = celu_d(z);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 3: 96 x 128 with the output layer and delta3 = celu'(z3) W4
+    dq = quantize_tile<T>(sm.a2, kLdF2, kH2, sm.q, &sm.amax, tid, nthr) * ws[2];
+    for (int mt = wave; mt < 6; mt += nw) {
+        const floatx4 acc = mfma_tile_fp8<T, 4>(fr + (F::F3 + mt * 4) * 64, sm.q, lane);
+        float part = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mt * 16 + rq + i;
+            const float z = acc[i] * dq + w[L::B3 + o];
+            const float w4 = w[L::W4 + o];
+            part += w4 * celu_f(z);
+            if (live) sm.a3[col * kLdF3 + o] = celu_d(z) * w4;
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (lane < 16) sm.ep[mt * 16 + lane] = part;
+    }
+    __syncthreads();
+    if (tid < T) {
+        float s = w[L::B4];
+        for (int mt = 0; mt < 6; ++mt) s += sm.ep[mt * 16 + tid];
+        E[tid] = s;
+    }
+    if (!GRAD) return;
+    // delta2 = celu'(z2) * W3^T delta3
+    dq = quantize_tile<T>(sm.a3, kLdF3, kH3, sm.q, &sm.amax, tid, nthr) * ws[3];
+    for (int mt = wave; mt < 8; mt += nw) {
+        const floatx4 acc = mfma_tile_fp8<T, 3>(fr + (F::B3 + mt * 3) * 64, sm.q, lane);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                sm.a2[col * kLdF2 + o] = acc[i] * dq * sm.d2[col * kLdF2 + o];
+            }
+        }
+    }
+    __syncthreads();
+    // delta1 = celu'(z1) * W2^T delta2
+    dq = quantize_tile<T>(sm.a2, kLdF2, kH2, sm.q, &sm.amax, tid, nthr) * ws[4];
+    for (int mt = wave; mt < 10; mt += nw) {
+        const floatx4 acc = mfma_tile_fp8<T, 4>(fr + (F::B2 + mt * 4) * 64, sm.q, lane);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int o = mt * 16 + rq + i;
+                sm.a1[col * kLdF1 + o] = acc[i] * dq * sm.d1[col * kLdF1 + o];
+            }
+        }
+    }
+    __syncthreads();
+    // dE/dG = W1^T delta1
+    dq = quantize_tile<T>(sm.a1, kLdF1, kH1, sm.q, &sm.amax, tid, nthr) * ws[5];
+    for (int mt = wave; mt < 24; mt += nw) {
+        const floatx4 acc = mfma_tile_fp8<T, 5>(fr + (F::B1 + mt * 5) * 64, sm.q, lane);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) G[col * kLdG + mt * 16 + rq + i] = acc[i] * dq;
+        }
+    }
+    __syncthreads();
+}
+
 }  // namespace nnp

@@ -126,7 +126,9 @@ struct Sys {
     double* stage;    // [3 n] staging for positions in caller order
     StepState* st;
     const float* w32;   // 4 * W32Layout::Stride floats
-    const void* wfrag;  // 4 * FragLayout::Count fragments of 1 KiB
+    const void* wfrag;  // 4 * 2 * FragLayout::Count BF16 fragments of 1 KiB (hi, lo)
+    const void* wfrag8; // 4 * FragLayout::Count E4M3 fragments of 512 B
+    const float* wscale8;  // [4][6] inverse E4M3 weight scales (layers F1 F2 F3 B3 B2 B1)
     // plain-path intermediates
     float* G;   // [n][384]
     float* dG;  // [n][384]

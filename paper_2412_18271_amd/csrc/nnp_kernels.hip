@@ -32,6 +32,10 @@ template <int T>
 struct MlpSmemOf<T, 2> {
     using type = MlpMfmaSmem<T, true>;
 };
+template <int T>
+struct MlpSmemOf<T, 3> {
+    using type = MlpFp8Smem<T>;
+};
 
 template <int T, int MODE, bool GRAD>
 __device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typename MlpSmemOf<T, MODE>::type& sm,
@@ -40,6 +44,9 @@ __device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typena
     const float* w = S.w32 + (size_t)elem * W32Layout::Stride;
     if constexpr (MODE == 0) {
         mlp_f32<T, GRAD>(w, G, sm, E, tid, 64 * T);
+    } else if constexpr (MODE == 3) {
+        const long* fr = reinterpret_cast<const long*>(S.wfrag8) + (size_t)elem * FragLayout::Count * 64;
+        mlp_fp8<T, GRAD>(w, fr, S.wscale8 + 6 * elem, G, sm, E, tid, 64 * T);
     } else {
         const bf16x8* fr = reinterpret_cast<const bf16x8*>(S.wfrag) + (size_t)elem * 2 * FragLayout::Count * 64;
         split_g_inplace<T, MODE == 2>(G, tid, 64 * T);
@@ -639,6 +646,8 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(8, 1)
         NNP_FUSED(4, 2)
         NNP_FUSED(8, 2)
+        NNP_FUSED(4, 3)
+        NNP_FUSED(8, 3)
 #undef NNP_FUSED
         return hipErrorInvalidValue;
     }
@@ -654,6 +663,8 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
     NNP_MLP(16, 1)
     NNP_MLP(8, 2)
     NNP_MLP(16, 2)
+    NNP_MLP(8, 3)
+    NNP_MLP(16, 3)
     if (e != hipSuccess) return e;
     if (grad) hipLaunchKernelGGL(k_adjoint, dim3(nb4), dim3(256), 0, s, S);
     return hipGetLastError();
@@ -678,6 +689,8 @@ hipError_t launch_store_forward(const Sys& S, int mode, int T, hipStream_t s)
     NNP_MLP(16, 1)
     NNP_MLP(8, 2)
     NNP_MLP(16, 2)
+    NNP_MLP(8, 3)
+    NNP_MLP(16, 3)
     return e;
 }
 
@@ -708,6 +721,22 @@ hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s)
 hipError_t launch_energy_out(const Sys& S, double* dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_energy_out, dim3((S.nmol + 255) / 256), dim3(256), 0, s, S, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_fp8_encode(const float* x, int n, unsigned char* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * i >= n) return;
+    const float b = 2 * i + 1 < n ? x[2 * i + 1] : 0.f;
+    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2 * i], b, 0, false);
+    out[2 * i] = (unsigned char)(w & 0xff);
+    if (2 * i + 1 < n) out[2 * i + 1] = (unsigned char)((w >> 8) & 0xff);
+}
+
+hipError_t launch_fp8_encode(const float* x, int n, unsigned char* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fp8_encode, dim3((n + 511) / 512), dim3(256), 0, s, x, n, out);
     return hipGetLastError();
 }
 

@@ -7,7 +7,8 @@ namespace nnp {
 
 // One energy (and, if grad, force) evaluation at the current positions.
 // path 0 = plain (one kernel per stage), 1 = fused; mode 0 = FP32 VALU,
-// 1 = BF16 MFMA, 2 = split BF16 MFMA (hi/lo operands, three products).
+// 1 = BF16 MFMA, 2 = split BF16 MFMA (hi/lo operands, three products),
+// 3 = E4M3 MFMA with per-layer scales.
 hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s);
 // Force gather + velocity Verlet + energies + step-state update (see kernel).
 hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces = true);
@@ -20,6 +21,8 @@ hipError_t launch_positions_in(const Sys& S, const void* src, int is_f64, hipStr
 hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s);
 hipError_t launch_energy_out(const Sys& S, double* dst, hipStream_t s);
 hipError_t launch_invalidate_lists(const Sys& S, hipStream_t s);
+// E4M3 encoding of n floats by the device conversion instruction (format check).
+hipError_t launch_fp8_encode(const float* x, int n, unsigned char* out, hipStream_t s);
 hipError_t launch_descriptors_only(const Sys& S, hipStream_t s);
 
 }  // namespace nnp

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "nnp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"\b(nnp_[a-z_]+)\s*\(", src))
+    names = set(re.findall(r"\b(nnp_[a-z0-9_]+)\s*\(", src))
     return names
 
 
@@ -68,7 +68,6 @@ def _params(P, s, **kw):
     ("n_atoms", 0, 1),
     ("n_molecules", 0, 1),
     ("weights_count", 10, 1),
-    ("mlp_dtype", 2, 3),
     ("mlp_dtype", 7, 1),
     ("path", 5, 1),
     ("rebuild_every", 0, 1),
@@ -120,3 +119,40 @@ def test_null_context_calls_fail_cleanly():
     assert lib.nnp_step(None, 0.5, 1, 0) == 1
     assert lib.nnp_set_state(None, None, None) == 1
     lib.nnp_destroy(None)
+
+
+def _e4m3_decode(b):
+    """OCP FP8 E4M3 value of code b (bias 7, 0x7f / 0xff NaN)."""
+    s = -1.0 if b & 0x80 else 1.0
+    e, m = (b >> 3) & 0xF, b & 7
+    if e == 0xF and m == 7:
+        return float("nan")
+    if e == 0:
+        return s * m * 2.0 ** -9
+    return s * (1 + m / 8.0) * 2.0 ** (e - 7)
+
+
+def test_host_e4m3_encoder_rounds_to_nearest_even():
+    """The host encoder (used for the FP8 weights) against the format's
+    definition: every finite code decodes and re-encodes to itself, values
+    beyond 448 saturate, and midpoints between neighbours round to even."""
+    import paper_2412_18271_amd as P
+    lib = P.load()
+    codes = [b for b in range(256) if not np.isnan(_e4m3_decode(b))]
+    vals = np.array([_e4m3_decode(b) for b in codes], np.float32)
+    out = np.zeros(len(vals), np.uint8)
+    assert lib.nnp_debug_fp8_encode(vals.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(vals),
+                                    None, out.ctypes.data) == 0
+    for b, o in zip(codes, out):
+        assert o == b or (b == 0x80 and o == 0x80) or (_e4m3_decode(b) == 0 and _e4m3_decode(o) == 0)
+    pos = sorted({_e4m3_decode(b) for b in codes if _e4m3_decode(b) > 0})
+    mids = np.array([(a + c) / 2 for a, c in zip(pos[:-1], pos[1:])] + [500.0, 1e6], np.float32)
+    out = np.zeros(len(mids), np.uint8)
+    lib.nnp_debug_fp8_encode(mids.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(mids), None, out.ctypes.data)
+    for x, o in zip(mids[:-2], out[:-2]):
+        lo = max(v for v in pos if v <= x)
+        hi = min(v for v in pos if v >= x)
+        got = _e4m3_decode(int(o))
+        assert got in (lo, hi)
+        assert int(o) & 1 == 0, (x, got)  # exact ties go to the even code
+    assert _e4m3_decode(int(out[-1])) == 448.0 and _e4m3_decode(int(out[-2])) == 448.0

@@ -129,3 +129,38 @@ def test_graph_replay_is_bitwise_equal_to_eager(make_system):
         ctx.close()
     assert np.array_equal(out[0]["pos"], out[1]["pos"])
     assert np.array_equal(out[0]["vel"], out[1]["vel"])
+
+
+def test_fp8_device_conversion_matches_host_encoder():
+    """The device E4M3 conversion (activations) and the host encoder
+    (weights) agree on every finite code, on midpoints and on values below
+    the smallest subnormal and above 448 (OCP E4M3, not the FNUZ variant)."""
+    import ctypes
+    import paper_2412_18271_amd as P
+    lib = P.load()
+    rng = np.random.Generator(np.random.PCG64(3))
+    x = np.concatenate([rng.normal(size=4000) * s for s in (1e-3, 1e-1, 10.0, 300.0)] +
+                       [np.array([0.0, -0.0, 448.0, -448.0, 2.0 ** -9, 2.0 ** -10, 2.0 ** -6])])
+    x = x[np.abs(x) < 460].astype(np.float32)
+    dev = np.zeros(x.shape[0], np.uint8)
+    host = np.zeros(x.shape[0], np.uint8)
+    assert lib.nnp_debug_fp8_encode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), x.shape[0],
+                                    dev.ctypes.data, host.ctypes.data) == 0
+    same = (dev == host) | ((dev & 0x7f) == 0) & ((host & 0x7f) == 0)
+    _say("fp8: %d of %d encodings agree" % (same.sum(), x.shape[0]))
+    assert same.all()
+
+
+@pytest.mark.parametrize("path", ["fused", "plain"])
+def test_fp8_network_error_reported(oracle_cache, path):
+    """FP8 (E4M3) network: errors against the oracle are reported; the
+    path must stay finite and within an order of magnitude of BF16's."""
+    s, Eo, Eio, Fo = oracle_cache("cluster2500")
+    ctx = _ctx(s, path=path, dtype="fp8")
+    E, F = ctx.compute(s.pos)
+    dE = abs(E.sum() - Eo.sum()) / np.abs(Eio).sum()
+    dF = np.abs(F - Fo).max()
+    _say("fp8 %s: |dE|/S %.3e  max|dF| %.3e  rms|dF| %.3e" % (path, dE, dF, np.sqrt(((F - Fo) ** 2).mean())))
+    assert np.all(np.isfinite(F))
+    assert dF <= 0.3
+    ctx.close()
