@@ -14,16 +14,30 @@ Variants (all through the C ABI, multi-step blocks replayed from HIP graphs):
   fp32  / fused   one kernel per evaluation, FP32 network on the vector ALUs
   bf16  / fused   one kernel per evaluation, BF16 MFMA network
   bf16x3/ fused   one kernel per evaluation, split-BF16 MFMA network
+  fp8   / fused   one kernel per evaluation, FP8 (E4M3) MFMA network
 The headline value is the fastest variant whose max force error against the
-FP64 oracle is <= 1e-2 eV/A.
+FP64 oracle is <= 1e-2 eV/A on the initial configuration and on 10 snapshots
+of a trajectory (the rerun check).
+
+Per variant the timed region is K graph-replayed steps after W warm-up steps;
+the same K steps are then replayed from the same state without a graph, with
+HIP events on the context stream around every kernel launch, which gives the
+average duration of the evaluation kernel for the roofline report.
+
+Other modes (not part of the default run): --precision (errors per network
+dtype on a second 2,500-atom cluster and on 23,000 atoms, and NVE drift),
+--profile-only (one variant's steps, for rocprofv3), --pmc-summary (turns
+two rocprofv3 counter databases into the traffic summary kept in profiles/).
 
 Prints ONE JSON line on stdout.
 """
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
+import sqlite3
 import sys
 import time
 
@@ -34,7 +48,9 @@ sys.path.insert(0, ROOT)
 
 DT_FS = 0.5
 F_TOL = 1e-2
-VARIANTS = (("fp32", "plain"), ("fp32", "fused"), ("bf16", "fused"), ("bf16x3", "fused"))
+N_SNAPSHOTS = 10
+VARIANTS = (("fp32", "plain"), ("fp32", "fused"), ("bf16", "fused"), ("bf16x3", "fused"), ("fp8", "fused"))
+KERNEL_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp8": 3}  # template MODE of k_eval_fused
 
 # Algorithmic FLOPs (see the design notes): per radial pair (r < 5.2 A) and
 # per angular triple (both neighbours within 3.5 A), forward descriptor plus
@@ -45,10 +61,24 @@ FLOP_MLP_ATOM = 2 * 2 * (384 * 160 + 160 * 128 + 128 * 96 + 96)
 
 MI355X_FP32_VECTOR_TFLOPS = 157.3
 MI355X_BF16_MFMA_TFLOPS = 2500.0
+MI355X_FP8_MFMA_TFLOPS = 5000.0
+MI355X_HBM_GBS = 8000.0
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_fused_cluster2500_traffic.md")
+KERNEL_SOURCES = ("nnp_kernels.hip", "nnp_device.h", "nnp_internal.h")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """sha256 over the sources the evaluation kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_18271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def neighbour_counts(pos):
@@ -67,11 +97,51 @@ def drift(U, K, n_atoms):
     return float(np.max(np.abs(H - H[0]))), float(slope * 1e3 / n_atoms)
 
 
-def run_variant(P, s, dtype, path, steps, warmup, F_ref):
+def snapshots(P, s, n, block):
+    """Positions every `block` steps of an FP32 trajectory (rerun inputs)."""
+    ctx = P.Context.from_system(s, dtype="fp32", path="fused")
+    try:
+        ctx.set_state(s.pos, s.vel)
+        out = []
+        for _ in range(n):
+            ctx.step(DT_FS, block, graph=True)
+            out.append(ctx.get_state()["pos"])
+        return out
+    finally:
+        ctx.close()
+
+
+def event_timed(ctx, s, warmup, steps):
+    """The timed segment again, without a graph: per-kernel averages from HIP
+    events, and the radial-pair / triple counts along it (mean of chunk ends)."""
+    ctx.set_state(s.pos, s.vel)
+    ctx.step(DT_FS, warmup, graph=True)
+    c0 = neighbour_counts(ctx.get_state()["pos"])
+    ev = ga = tot = 0.0
+    rad = tri = 0.0
+    left = steps
+    while left > 0:
+        n = min(100, left)
+        a, b, c = ctx.time_steps(DT_FS, n)
+        c1 = neighbour_counts(ctx.get_state()["pos"])
+        ev += a * n
+        ga += b * n
+        tot += c * n
+        rad += 0.5 * (c0[0] + c1[0]) * n
+        tri += 0.5 * (c0[1] + c1[1]) * n
+        c0 = c1
+        left -= n
+    return {"eval_ms": ev / steps, "gather_ms": ga / steps, "step_ms_eager": tot / steps,
+            "radial_pairs": rad / steps, "angular_triples": tri / steps}
+
+
+def run_variant(P, s, dtype, path, steps, warmup, refs):
     ctx = P.Context.from_system(s, dtype=dtype, path=path)
     try:
-        E, F = ctx.compute(s.pos)
-        ferr = float(np.abs(F - F_ref).max()) if F_ref is not None else None
+        errs = []
+        for pos, F_ref in refs:
+            _, F = ctx.compute(pos)
+            errs.append(float(np.abs(F - F_ref).max()))
         ctx.set_state(s.pos, s.vel)
         ctx.step(DT_FS, warmup, graph=True)
         ctx.stats()  # synchronises
@@ -81,36 +151,153 @@ def run_variant(P, s, dtype, path, steps, warmup, F_ref):
         t1 = time.perf_counter()
         U, K = ctx.energy_log(min(steps + 1, 4096))
         dH, slope = drift(U[:, 0], K[:, 0], s.n_atoms)
-        state = ctx.get_state()
-        ms_eval, ms_gather = ctx.time_kernels(50)
+        final_finite = bool(np.isfinite(ctx.get_state()["pos"]).all())
+        kt = event_timed(ctx, s, warmup, steps)
         return {
             "dtype": dtype, "path": path, "steps_per_s": steps / (t1 - t0),
-            "ms_per_step": 1e3 * (t1 - t0) / steps, "max_force_err": ferr,
+            "ms_per_step": 1e3 * (t1 - t0) / steps, "max_force_err": errs[0],
+            "max_force_err_snapshots": max(errs[1:]) if len(errs) > 1 else None,
             "drift_max_abs_eV": dH, "drift_slope_meV_per_atom_ps": slope,
             "rebuilds": st["rebuilds"], "forced_rebuilds": st["forced_rebuilds"],
-            "kernel_ms_eval": ms_eval, "kernel_ms_gather_vv": ms_gather,
-            "final_finite": bool(np.isfinite(state["pos"]).all()),
+            "kernel_ms_eval": kt["eval_ms"], "kernel_ms_gather_vv": kt["gather_ms"],
+            "step_ms_eager": kt["step_ms_eager"], "radial_pairs_mean": kt["radial_pairs"],
+            "angular_triples_mean": kt["angular_triples"], "final_finite": final_finite,
         }
     finally:
         ctx.close()
 
 
+def batch_leg(P, steps, warmup):
+    """256 molecules of 10-300 atoms: molecule-steps/s of one batched context
+    (one evaluation launch per step for all molecules, graph-replayed) against
+    a loop of one context per molecule (graph-replayed, and eager)."""
+    import synth
+    s = synth.make_config("batch256")
+    M = s.n_molecules
+    out = {"n_molecules": M, "n_atoms": int(s.n_atoms), "steps": steps, "dtype": "bf16x3"}
+    ctx = P.Context.from_system(s, dtype="bf16x3", path="fused")
+    try:
+        ctx.set_state(s.pos, s.vel)
+        ctx.step(DT_FS, warmup, graph=True)
+        ctx.stats()
+        t0 = time.perf_counter()
+        ctx.step(DT_FS, steps, graph=True)
+        ctx.stats()
+        out["batched_molecule_steps_per_s"] = M * steps / (time.perf_counter() - t0)
+    finally:
+        ctx.close()
+    ctxs = []
+    try:
+        for m in range(M):
+            sl = s.molecule(m)
+            c = P.Context(s.species[sl], s.masses[sl], s.weights, None, dtype="bf16x3", path="fused")
+            c.set_state(s.pos[sl], s.vel[sl])
+            ctxs.append(c)
+        for graph, key in ((True, "per_molecule_graph_molecule_steps_per_s"),
+                           (False, "per_molecule_eager_molecule_steps_per_s")):
+            for c in ctxs:
+                c.step(DT_FS, warmup, graph=graph)
+            for c in ctxs:
+                c.stats()
+            t0 = time.perf_counter()
+            for c in ctxs:
+                c.step(DT_FS, steps, graph=graph)
+            for c in ctxs:
+                c.stats()
+            out[key] = M * steps / (time.perf_counter() - t0)
+    finally:
+        for c in ctxs:
+            c.close()
+    out["speedup_vs_per_molecule_graph"] = (out["batched_molecule_steps_per_s"]
+                                            / out["per_molecule_graph_molecule_steps_per_s"])
+    return out
+
+
 def copy_calibration(mib):
-    """One device-to-device copy of a known size (the HIP runtime's blit
-    kernel), to scale the FETCH_SIZE / WRITE_SIZE counters of a profile."""
-    import ctypes
-    hip = ctypes.CDLL("libamdhip64.so")
-    n = int(mib) << 20
-    a, b = ctypes.c_void_p(), ctypes.c_void_p()
-    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(n)) == 0
-    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(n)) == 0
-    assert hip.hipMemset(a, 1, ctypes.c_size_t(n)) == 0
+    """One elementwise kernel of known traffic (reads and writes `mib` MiB),
+    to scale the FETCH_SIZE / WRITE_SIZE counters of a profile."""
+    import torch
+    n = (int(mib) << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
     for _ in range(3):
-        assert hip.hipMemcpy(b, a, ctypes.c_size_t(n), 3) == 0  # device to device
-    assert hip.hipDeviceSynchronize() == 0
-    hip.hipFree(a)
-    hip.hipFree(b)
-    log("copy calibration: 3 x %d MiB device-to-device" % mib)
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x torch.neg over %d MiB (read %d MiB, write %d MiB)" % (mib, mib, mib))
+
+
+def pmc_summary(fetch_db, write_db, variant, mib, command):
+    """Markdown summary of a FETCH_SIZE run and a WRITE_SIZE run: per-dispatch
+    KiB of the evaluation kernel, scaled by the calibration kernel's reading."""
+    dtype, path = variant.split(":")
+    pat = "k_eval_fused<%s, %d," if path == "fused" else "k_mlp<%s, %d,"
+
+    def per_kernel(db, counter):
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                         (counter,)).fetchall()
+        return rows
+
+    known_kib = mib * 1024.0
+    res = {}
+    for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        rows = per_kernel(db, counter)
+        cal = [v for k, v in rows if "neg" in k and v > 0.25 * known_kib]
+        ker = [(k, v) for k, v in rows if "k_eval_fused" in k or "k_mlp" in k]
+        names = sorted({k for k, _ in ker})
+        mine = [v for k, v in ker if re.search(r"k_eval_fused<\d+, %d," % KERNEL_MODE[dtype], k)]
+        res[counter] = {"cal_kib": float(np.median(cal)) if cal else None,
+                        "kernel_kib": float(np.mean(mine)) if mine else None,
+                        "dispatches": len(mine), "names": names}
+    fr = res["FETCH_SIZE"]
+    wr = res["WRITE_SIZE"]
+    f_factor = known_kib / fr["cal_kib"]
+    w_factor = known_kib / wr["cal_kib"]
+    fetch_b = fr["kernel_kib"] * f_factor * 1024
+    write_b = wr["kernel_kib"] * w_factor * 1024
+    lines = [
+        "# k_eval_fused HBM traffic, cluster2500 (2,500 atoms), %s network" % dtype,
+        "",
+        "Commands (run from the repository root, TMPDIR=/tmp):",
+        "",
+        "```",
+        command.replace("COUNTER", "FETCH_SIZE"),
+        command.replace("COUNTER", "WRITE_SIZE"),
+        "python3 bench.py --pmc-summary <fetch run db> <write run db> --variant %s --copy-calibration-mib %d"
+        % (variant, mib),
+        "```",
+        "",
+        "Calibration kernel: torch.neg over %d MiB of float32 (reads %d MiB, writes %d MiB)." % (mib, mib, mib),
+        "",
+        "| counter | calibration reading (KiB) | known (KiB) | scale | k_eval_fused per dispatch (KiB) | dispatches | scaled bytes per launch |",
+        "|---|---|---|---|---|---|---|",
+        "| FETCH_SIZE | %.1f | %.0f | %.4f | %.1f | %d | %.0f |" % (fr["cal_kib"], known_kib, f_factor,
+                                                                  fr["kernel_kib"], fr["dispatches"], fetch_b),
+        "| WRITE_SIZE | %.1f | %.0f | %.4f | %.1f | %d | %.0f |" % (wr["cal_kib"], known_kib, w_factor,
+                                                                  wr["kernel_kib"], wr["dispatches"], write_b),
+        "",
+        "Kernels seen: %s" % ", ".join(fr["names"]),
+        "",
+        "- variant: %s" % variant,
+        "- hbm_bytes_per_launch: %d" % int(round(fetch_b + write_b)),
+        "- fetch_bytes_per_launch: %d" % int(round(fetch_b)),
+        "- write_bytes_per_launch: %d" % int(round(write_b)),
+        "- kernel_source_sha256: %s" % kernel_source_hash(),
+    ]
+    print("\n".join(lines))
+
+
+def load_traffic(variant):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it covers another variant or the kernel sources changed since."""
+    try:
+        txt = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
+    if kv.get("variant") != variant or kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return int(kv["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(s, seconds):
@@ -123,9 +310,86 @@ def cpu_baseline(s, seconds):
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    # one core, a few evaluations
+    oracle.set_threads(1)
+    n1 = 0
+    t1 = time.perf_counter()
+    while n1 < 2 or time.perf_counter() - t1 < min(5.0, seconds / 3):
+        oracle.energy_forces(s.pos, s.species, s.weights)
+        n1 += 1
+    one = n1 / (time.perf_counter() - t1)
+    oracle.set_threads(cores)
+    return {"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": "%d FP64 energy+force evaluations of the 2,500-atom cluster at its initial "
-                      "positions (no integration), %.1f s" % (n, dt)}
+                      "positions (no integration), %.1f s on %d threads; one thread: %.2f evals/s"
+                      % (n, dt, cores, one),
+            "single_core_value": one}
+
+
+def nve_energies(ctx, s, n, chunk=2000):
+    """H = U + K at every step of an n-step NVE run from the initial state
+    (the device keeps the last 4096 steps; read after every chunk)."""
+    ctx.set_state(s.pos, s.vel)
+    H = []
+    done = 0
+    while done < n:
+        c = min(chunk, n - done)
+        ctx.step(DT_FS, c, graph=True)
+        U, K = ctx.energy_log(c + 1 if done == 0 else c)
+        H.append(U[:, 0] + K[:, 0])
+        done += c
+    return np.concatenate(H)
+
+
+def precision_study(P, steps_drift):
+    """Force / energy errors per network dtype against the oracle, and NVE
+    drift over `steps_drift` steps, on a second 2,500-atom cluster and on
+    23,000 atoms (sampled atoms there)."""
+    import oracle
+    import synth
+    out = {}
+    for name in ("cluster2500b", "cluster23k"):
+        s = synth.make_config(name)
+        res = {"n_atoms": int(s.n_atoms)}
+        if s.n_atoms <= 5000:
+            Eo, Eio, Fo = oracle.energy_forces(s.pos, s.species, s.weights)
+            sel = np.arange(s.n_atoms)
+        else:
+            Eo, Eio, _ = oracle.energy_forces(s.pos, s.species, s.weights, forces=False)
+            rng = np.random.Generator(np.random.PCG64(5))
+            sel = np.sort(rng.choice(s.n_atoms, size=64, replace=False))
+            Fo = np.zeros((s.n_atoms, 3))
+            for a in sel:
+                env = oracle.local_environment(s.pos, int(a), 10.4)
+                loc = int(np.nonzero(env == a)[0][0])
+                Fo[a] = oracle.forces_on(s.pos[env], s.species[env], s.weights, [loc])[0]
+        S = float(np.abs(Eio).sum())
+        for dtype in ("fp32", "bf16x3", "bf16", "fp8"):
+            ctx = P.Context.from_system(s, dtype=dtype, path="fused")
+            try:
+                E, F = ctx.compute(s.pos)
+                r = {"rel_energy_err": float(abs(E[0] - Eo) / S),
+                     "max_force_err": float(np.abs(F[sel] - Fo[sel]).max()),
+                     "rms_force_err": float(np.sqrt(np.mean((F[sel] - Fo[sel]) ** 2))),
+                     "force_atoms_checked": int(len(sel))}
+                n = steps_drift
+                t0 = time.perf_counter()
+                H = nve_energies(ctx, s, n)
+                r["drift_steps"] = n
+                r["drift_steps_per_s"] = n / (time.perf_counter() - t0)
+                t = np.arange(H.shape[0]) * DT_FS * 1e-3
+                r["drift_max_abs_eV"] = float(np.max(np.abs(H - H[0])))
+                r["drift_slope_meV_per_atom_ps"] = float(np.polyfit(t, H, 1)[0] * 1e3 / s.n_atoms)
+                r["stats"] = ctx.stats()
+            except Exception as e:  # report the failure for this dtype
+                r = {"error": str(e)}
+            finally:
+                ctx.close()
+            log(name, dtype, json.dumps(r))
+            res[dtype] = r
+        out[name] = res
+    return out
 
 
 def main():
@@ -135,19 +399,37 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--variants", default=",".join("%s:%s" % v for v in VARIANTS))
     ap.add_argument("--profile-only", default=None,
                     help="dtype:path; run only that variant's timed steps (for rocprofv3)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="with --profile-only: also run a device-to-device copy of this size")
+                    help="with --profile-only: also run an elementwise kernel over this many MiB")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None)
+    ap.add_argument("--variant", default="bf16x3:fused", help="with --pmc-summary")
+    ap.add_argument("--pmc-command", default="timeout -s KILL 60 rocprofv3 --pmc COUNTER -d <dir> -o run -- "
+                    "python3 bench.py --profile-only bf16x3:fused --steps 20 --warmup 5 "
+                    "--copy-calibration-mib 256")
+    ap.add_argument("--precision", action="store_true",
+                    help="run the precision / drift study instead of the benchmark")
+    ap.add_argument("--drift-steps", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.variant,
+                    args.copy_calibration_mib or 256, args.pmc_command)
+        return
+
     import synth
     import paper_2412_18271_amd as P
+
+    if args.precision:
+        print(json.dumps({"precision_study": precision_study(P, args.drift_steps)}), flush=True)
+        return
 
     s = synth.make_config("cluster2500")
     if args.profile_only:
@@ -163,33 +445,41 @@ def main():
         return
 
     import oracle
-    log("oracle forces at the initial configuration")
-    _, _, F_ref = oracle.energy_forces(s.pos, s.species, s.weights)
+    log("oracle forces at the initial configuration and at %d trajectory snapshots" % N_SNAPSHOTS)
+    snaps = snapshots(P, s, N_SNAPSHOTS, 100)
+    refs = [(p, oracle.energy_forces(p, s.species, s.weights)[2]) for p in [s.pos] + snaps]
     variants = [tuple(v.split(":")) for v in args.variants.split(",") if v]
     res = []
     for dtype, path in variants:
         log("variant", dtype, path)
-        r = run_variant(P, s, dtype, path, args.steps, args.warmup, F_ref)
+        r = run_variant(P, s, dtype, path, args.steps, args.warmup, refs)
         log("  ", json.dumps(r))
         res.append(r)
-    ok = [r for r in res if r["max_force_err"] is not None and r["max_force_err"] <= F_TOL]
+    ok = [r for r in res if r["max_force_err"] <= F_TOL
+          and (r["max_force_err_snapshots"] is None or r["max_force_err_snapshots"] <= F_TOL)]
     best = max(ok, key=lambda r: r["steps_per_s"])
     plain = next((r for r in res if r["dtype"] == "fp32" and r["path"] == "plain"), None)
 
-    rad, tri = neighbour_counts(s.pos)
+    rad, tri = best["radial_pairs_mean"], best["angular_triples_mean"]
     valu_flop = rad * FLOP_RADIAL_PAIR + tri * FLOP_ANGULAR_TRIPLE
     mlp_flop = s.n_atoms * FLOP_MLP_ATOM
     t_eval = best["kernel_ms_eval"] * 1e-3
     valu_tflops = valu_flop / t_eval / 1e12
+    mfma_peak = MI355X_FP8_MFMA_TFLOPS if best["dtype"] == "fp8" else MI355X_BF16_MFMA_TFLOPS
+    mlp_peak = MI355X_FP32_VECTOR_TFLOPS if best["dtype"] == "fp32" else mfma_peak
+    traffic = load_traffic("%s:%s" % (best["dtype"], best["path"]))
+    sol_s = valu_flop / (MI355X_FP32_VECTOR_TFLOPS * 1e12) + mlp_flop / (mlp_peak * 1e12)
     roofline = {
-        "kernel": "k_eval_fused (%s network): descriptors + network + adjoint" % best["dtype"],
         "bound": "alu", "achieved": valu_tflops, "peak": MI355X_FP32_VECTOR_TFLOPS,
-        "unit": "TFLOP/s", "frac": valu_tflops / MI355X_FP32_VECTOR_TFLOPS, "traffic": None,
-        "flop_per_launch_valu": valu_flop, "flop_per_launch_mlp": mlp_flop,
-        "mlp_tflops": mlp_flop / t_eval / 1e12,
-        "mlp_frac_of_bf16_mfma_peak": mlp_flop / t_eval / 1e12 / MI355X_BF16_MFMA_TFLOPS,
+        "unit": "TFLOP/s", "frac": valu_tflops / MI355X_FP32_VECTOR_TFLOPS, "traffic": traffic,
+        "kernel": "k_eval_fused (%s network): descriptors + network + adjoint" % best["dtype"],
         "kernel_ms": best["kernel_ms_eval"],
-        "radial_pairs": rad, "angular_triples": tri,
+        "flop_per_launch_valu": valu_flop, "flop_per_launch_mlp": mlp_flop,
+        "radial_pairs_per_launch": rad, "angular_triples_per_launch": tri,
+        "mlp_tflops": mlp_flop / t_eval / 1e12, "mlp_peak_tflops": mlp_peak,
+        "mlp_frac": mlp_flop / t_eval / 1e12 / mlp_peak,
+        "speed_of_light_us": sol_s * 1e6, "speed_of_light_frac": sol_s / t_eval,
+        "hbm_gbs_from_traffic": None if traffic is None else traffic / t_eval / 1e9,
     }
     out = {
         "metric": "NNP energy+force evals/s & ns/day (2.5k atoms), BF16-MFMA vs FP32 plain",
@@ -207,6 +497,10 @@ def main():
         "variants": res,
         "roofline": roofline,
     }
+    if not args.no_batch:
+        log("batch256")
+        out["batch256"] = batch_leg(P, 100, 20)
+        log("  ", json.dumps(out["batch256"]))
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)

@@ -216,6 +216,17 @@ nnp_status nnp_autotune(nnp_context* ctx, const char* cache_path);
  * launch of each.  Used by the benchmark's roofline report.  Synchronises. */
 nnp_status nnp_time_kernels(nnp_context* ctx, int32_t reps, double* ms);
 
+/* Event-timed MD: runs n_steps velocity-Verlet steps like nnp_step without
+ * a graph, recording a HIP event on the context stream before every
+ * evaluation launch, between it and the force-gather / integration launch,
+ * and after the last step.  ms[0] receives the average milliseconds of the
+ * evaluation kernel(s) per step, ms[1] that of the gather / integration
+ * kernel, ms[2] the average wall time per step between the first and the
+ * last event.  The trajectory advances exactly as with nnp_step (pair-list
+ * rebuilds included).  Used by the benchmark's roofline report.
+ * Synchronises; n_steps >= 1, dt > 0. */
+nnp_status nnp_time_steps(nnp_context* ctx, double dt_fs, int32_t n_steps, double* ms);
+
 /* E4M3 encodings of x[n]: host_out by the library's host encoder (used for
  * the weights), device_out by the device conversion instruction (used for
  * activations); either may be NULL.  A format check, no context needed. */

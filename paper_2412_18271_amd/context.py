@@ -167,6 +167,13 @@ class Context:
     def autotune(self, cache_path: Optional[str] = None):
         self._check(self._lib.nnp_autotune(self._h, cache_path.encode() if cache_path else None))
 
+    def time_steps(self, dt: float, n: int):
+        """n event-timed MD steps without a graph: average ms per step of
+        (evaluation kernels, gather/integration kernel, whole step)."""
+        ms = np.zeros(3)
+        self._check(self._lib.nnp_time_steps(self._h, float(dt), int(n), _dptr(ms)))
+        return float(ms[0]), float(ms[1]), float(ms[2])
+
     def time_kernels(self, reps: int = 50):
         """Average ms per launch of (evaluation kernels, gather kernel)."""
         ms = np.zeros(2)

@@ -153,6 +153,31 @@ nnp_status check_positions(nnp_context* c, const double* pos)
     return NNP_OK;
 }
 
+// Tiles of at most T consecutive atoms of one element (atoms are element-major
+// in the internal order).  Workgroups are handed to the eight XCDs round-robin
+// (workgroup b runs on XCD b mod 8), so the table is permuted to give each XCD
+// one contiguous run of tiles: an XCD then meets one or two elements and its
+// L2 holds only their weight fragments.
+std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
+{
+    std::vector<int4> seq;
+    const int n = (int)elem.size();
+    for (int k = 0; k < n;) {
+        const int e = elem[k];
+        int k2 = k;
+        while (k2 < n && elem[k2] == e && k2 - k < T) ++k2;
+        seq.push_back(make_int4(k, k2 - k, e, 0));
+        k = k2;
+    }
+    const int nt = (int)seq.size(), q = nt / kXcds, r = nt % kXcds;
+    std::vector<int4> out(nt);
+    for (int b = 0; b < nt; ++b) {
+        const int x = b % kXcds, j = b / kXcds;
+        out[b] = seq[x * q + std::min(x, r) + j];
+    }
+    return out;
+}
+
 // Builds the internal order from the first positions and uploads every
 // per-atom constant.
 nnp_status lay_out(nnp_context* c, const double* pos)
@@ -203,15 +228,9 @@ nnp_status lay_out(nnp_context* c, const double* pos)
         mr[(size_t)m * 4 + e] = make_int2(k, k2);
         k = k2;
     }
-    // tiles: T consecutive atoms of one element
-    std::vector<int4> tiles;
-    for (int k = 0; k < n;) {
-        const int e = (int)p4[k].w;
-        int k2 = k;
-        while (k2 < n && (int)p4[k2].w == e && k2 - k < c->T) ++k2;
-        tiles.push_back(make_int4(k, k2 - k, e, 0));
-        k = k2;
-    }
+    std::vector<int> elem(n);
+    for (int k = 0; k < n; ++k) elem[k] = (int)p4[k].w;
+    const std::vector<int4> tiles = make_tiles(elem, c->T);
     std::vector<int> perm_dev(c->perm.begin(), c->perm.end());
     Sys& S = c->S;
     S.ntiles = (int)tiles.size();
@@ -291,15 +310,9 @@ nnp_status retile(nnp_context* c, int T)
 {
     c->T = T;
     if (!c->laid_out) return NNP_OK;
-    std::vector<int4> tiles;
-    const int n = c->n;
-    for (int k = 0; k < n;) {
-        const int e = c->species[c->perm[k]];
-        int k2 = k;
-        while (k2 < n && c->species[c->perm[k2]] == e && k2 - k < T) ++k2;
-        tiles.push_back(make_int4(k, k2 - k, e, 0));
-        k = k2;
-    }
+    std::vector<int> elem(c->n);
+    for (int k = 0; k < c->n; ++k) elem[k] = c->species[c->perm[k]];
+    const std::vector<int4> tiles = make_tiles(elem, T);
     c->S.ntiles = (int)tiles.size();
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipMemcpy((void*)c->S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
@@ -1032,6 +1045,50 @@ nnp_status nnp_time_kernels(nnp_context* c, int32_t reps, double* ms)
     ms[1] = b / reps;
     c->forces_current = true;
     c->kick_pending = false;
+    return check_device_flags(c);
+}
+
+nnp_status nnp_time_steps(nnp_context* c, double dt, int32_t nsteps, double* ms)
+{
+    if (!c || !ms || nsteps < 1) return fail(c, NNP_ERR_ARG, "bad arguments");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, NNP_ERR_ARG, "dt must be finite and > 0");
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before stepping");
+    c->diff_state = 0;
+    if (!c->forces_current) {
+        HIP_TRY(c, enqueue_compute(c, true));
+        c->forces_current = true;
+    }
+    // ev[2i] before evaluation i, ev[2i+1] between it and gather i, ev[2n] at the end
+    std::vector<hipEvent_t> ev(2 * (size_t)nsteps + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = launch_kickdrift(c->S, dt, c->stream);
+    for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
+        e = hipEventRecord(ev[2 * i], c->stream);
+        if (e == hipSuccess) e = enqueue_eval(c, true);
+        if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], c->stream);
+        if (e == hipSuccess) e = launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * nsteps], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * nsteps]);
+    double sum_eval = 0.0, sum_gather = 0.0;
+    for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]);
+        sum_eval += a;
+        sum_gather += b;
+    }
+    float total = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&total, ev[0], ev[2 * nsteps]);
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(c, e, "timed steps");
+    ms[0] = sum_eval / nsteps;
+    ms[1] = sum_gather / nsteps;
+    ms[2] = (double)total / nsteps;
+    c->kick_pending = true;
     return check_device_flags(c);
 }
 

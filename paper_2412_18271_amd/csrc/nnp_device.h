@@ -128,7 +128,7 @@ __device__ __forceinline__ void env_finish(const Sys& S, Env& E, int nR, int nA,
 
 // Rebuilds the pair list of atom a (all atoms of its molecule closer than
 // 5.2 + skin, ascending index) and fills its environment from the scan.
-__device__ void build_list_env(const Sys& S, int a, Env& E)
+__device__ __forceinline__ void build_list_env(const Sys& S, int a, Env& E)
 {
     const int lane = lane_id();
     const double4 pa = S.pos[a];
@@ -167,7 +167,7 @@ __device__ void build_list_env(const Sys& S, int a, Env& E)
 }
 
 // Builds only the pair list (plain path).
-__device__ void build_list(const Sys& S, int a)
+__device__ __forceinline__ void build_list(const Sys& S, int a)
 {
     const int lane = lane_id();
     const double4 pa = S.pos[a];
@@ -198,7 +198,7 @@ __device__ void build_list(const Sys& S, int a)
 }
 
 // Loads the environment of atom a from its existing pair list.
-__device__ void load_env(const Sys& S, int a, Env& E)
+__device__ __forceinline__ void load_env(const Sys& S, int a, Env& E)
 {
     const int lane = lane_id();
     const double4 pa = S.pos[a];
@@ -225,7 +225,7 @@ __device__ void load_env(const Sys& S, int a, Env& E)
 
 // Radial features G[0..63] of the wave's atom.  Lane (k, q): Gaussian k,
 // neighbour subset q of 4; per-element sums, then a reduction over q.
-__device__ void radial_features(const Env& E, float* G)
+__device__ __forceinline__ void radial_features(const Env& E, float* G)
 {
     const int lane = lane_id();
     const int k = lane & 15, q = lane >> 4;
@@ -298,20 +298,36 @@ __device__ __forceinline__ PairRun lane_run(const Env& E, int lane)
         cnt[p] = s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
         total += cnt[p];
     }
-    // run length C = 2^lc >= total / 48, so the runs fit in 48 + 10 lanes
-    int lc = 0;
-    while ((48 << lc) < total) ++lc;
-    const int C = 1 << lc;
+    // run length C: ceil(total / 64) when its runs fit in the 64 lanes (every
+    // lane busy), else max(that + 1, ceil(total / 54)), for which
+    // sum_p ceil(cnt_p / C) < total / C + 10 <= 64 always holds.  Ceilings
+    // use a float reciprocal with an exact integer correction.
+    int C = total > 64 ? (total + 63) >> 6 : 1;
+    int runs[10];
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        const float inv = __builtin_amdgcn_rcpf((float)C);
+        int sum = 0;
+#pragma unroll
+        for (int p = 0; p < 10; ++p) {
+            int r = (int)((float)cnt[p] * inv + 0.5f);
+            r += (r * C < cnt[p]) - ((r - 1) * C >= cnt[p] && r > 0);
+            runs[p] = r;
+            sum += r;
+        }
+        if (sum <= 64) break;
+        int c54 = (int)((float)total * (1.0f / 54.0f) + 0.5f);
+        c54 += (c54 * 54 < total) - ((c54 - 1) * 54 >= total && c54 > 0);
+        C = max(C + 1, c54);
+    }
     PairRun R;
     R.p = -1;
     R.left = 0;
     int first = 0, q0 = 0;
 #pragma unroll
     for (int p = 0; p < 10; ++p) {
-        const int runs = (cnt[p] + C - 1) >> lc;
-        if (lane >= first && lane < first + runs) {
+        if (lane >= first && lane < first + runs[p]) {
             const int s1 = kPairS1[p], s2 = kPairS2[p];
-            q0 = (lane - first) << lc;
+            q0 = (lane - first) * C;
             R.p = p;
             R.left = min(C, cnt[p] - q0);
             R.lo1 = seg[s1];
@@ -319,7 +335,7 @@ __device__ __forceinline__ PairRun lane_run(const Env& E, int lane)
             R.n2 = seg[s2 + 1] - seg[s2];
             R.same = s1 == s2;
         }
-        first += runs;
+        first += runs[p];
     }
     if (R.p >= 0) {
         if (R.same) {
@@ -336,74 +352,120 @@ __device__ __forceinline__ PairRun lane_run(const Env& E, int lane)
     return R;
 }
 
-__device__ __forceinline__ void run_pair(const PairRun& R, int& j, int& k)
-{
-    if (R.same) {
-        j = R.lo1 + R.jj;
-        k = R.lo1 + R.kk;
-    } else {
-        j = R.lo1 + R.jj;
-        k = R.lo2 + R.kk;
-    }
-}
+// A run walks its pairs with one index fixed for several steps: k in a
+// triangular group (pairs enumerated by k, then j < k), j otherwise.  x is
+// that slowly changing index, y the one that moves every step; the terms are
+// symmetric in the two neighbours, so (x, y) stands for (j, k) or (k, j).
+__device__ __forceinline__ int run_x(const PairRun& R) { return R.same ? R.lo1 + R.kk : R.lo1 + R.jj; }
+__device__ __forceinline__ int run_y(const PairRun& R) { return R.same ? R.lo1 + R.jj : R.lo2 + R.kk; }
 
-__device__ __forceinline__ void run_next(PairRun& R)
+// Advances to the next pair; true when x changed.
+__device__ __forceinline__ bool run_next(PairRun& R)
 {
     if (R.same) {
         if (++R.jj == R.kk) {
             ++R.kk;
             R.jj = 0;
+            return true;
         }
-    } else if (++R.kk == R.n2) {
+        return false;
+    }
+    if (++R.kk == R.n2) {
         R.kk = 0;
         ++R.jj;
+        return true;
     }
+    return false;
+}
+
+// Value of lane (lane - d) of the same row of 16 lanes, 0 for the first d
+// lanes of a row (DPP row shift).
+template <int D>
+__device__ __forceinline__ float row_shr(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 | D, 0xF, 0xF, false));
+}
+
+template <int D>
+__device__ __forceinline__ float same_group_shr(int p)
+{
+    const int q = __builtin_amdgcn_update_dpp(-2, p, 0x110 | D, 0xF, 0xF, false);
+    return (q == p && p >= 0) ? 1.f : 0.f;
 }
 
 // Angular features of the wave's atom, accumulated into acc[10][33] (LDS,
-// zeroed beforehand): each lane sums the 32 terms of its run in registers,
-// then adds them once; element-pair blocks 33 floats apart sit in different
-// banks.  The caller copies acc into G[64 + 32 p + f].
-__device__ void angular_features(const Env& E, float* acc)
+// zeroed beforehand).  Each lane sums the 32 terms of its run in registers;
+// runs of one element pair occupy consecutive lanes, so a segmented scan
+// inside each row of 16 lanes (DPP shifts 1, 2, 4, 8) leaves every
+// (row, element pair) total in the last lane of its segment, and only those
+// lanes add to LDS.  Element-pair blocks 33 floats apart sit in different
+// banks.  All 64 lanes execute the scan.  The caller copies acc into
+// G[64 + 32 p + f].
+__device__ __forceinline__ void angular_features(const Env& E, float* acc)
 {
     const int lane = lane_id();
     PairRun R = lane_run(E, lane);
-    if (R.p < 0) return;
     float t[32];
 #pragma unroll
     for (int f = 0; f < 32; ++f) t[f] = 0.f;
-    for (int it = 0; it < R.left; ++it) {
-        int j, k;
-        run_pair(R, j, k);
-        run_next(R);
-        const int ej = E.ang[j], ek = E.ang[k];
-        const float4 gj = E.geo[ej], gk = E.geo[ek];
-        const float c = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
-        const float cp = kCosScale * c;
-        const float sp = sqrtf(fmaxf(0.f, 1.f - cp * cp));
-        const float w = kTwoPowM31 * E.afc[j].x * E.afc[k].x;
-        const float rbar = 0.5f * (gj.w + gk.w);
-        float B[kNumShells];
+    if (R.p >= 0) {
+        int ex = E.ang[run_x(R)];
+        float4 gx = E.geo[ex];
+        float fx = E.afc[run_x(R)].x;
+        for (int it = 0; it < R.left; ++it) {
+            const int y = run_y(R);
+            const int ey = E.ang[y];
+            const float4 gy = E.geo[ey];
+            const float fy = E.afc[y].x;
+            const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
+            const float cp = kCosScale * c;
+            const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - cp * cp));
+            const float w = kTwoPowM31 * fx * fy;
+            const float rbar = 0.5f * (gx.w + gy.w);
+            float B[kNumShells];
 #pragma unroll
-        for (int m = 0; m < kNumShells; ++m) {
-            const float x = rbar - (0.9f + 0.65f * (float)m);
-            B[m] = w * __expf(-kEtaAng * x * x);
-        }
+            for (int m = 0; m < kNumShells; ++m) {
+                const float x = rbar - (0.9f + 0.65f * (float)m);
+                B[m] = w * __expf(-kEtaAng * x * x);
+            }
 #pragma unroll
-        for (int n = 0; n < kNumSectors; ++n) {
-            float u = 1.f + cp * kSecCos[n] + sp * kSecSin[n];
-            u = u * u;  // ^2
-            u = u * u;  // ^4
-            u = u * u;  // ^8
-            u = u * u;  // ^16
-            u = u * u;  // ^32
+            for (int n = 0; n < kNumSectors; ++n) {
+                float u = 1.f + cp * kSecCos[n] + sp * kSecSin[n];
+                u = u * u;  // ^2
+                u = u * u;  // ^4
+                u = u * u;  // ^8
+                u = u * u;  // ^16
+                u = u * u;  // ^32
 #pragma unroll
-            for (int m = 0; m < kNumShells; ++m) t[8 * m + n] += u * B[m];
+                for (int m = 0; m < kNumShells; ++m) t[8 * m + n] += u * B[m];
+            }
+            if (run_next(R) && it + 1 < R.left) {
+                const int x = run_x(R);
+                ex = E.ang[x];
+                gx = E.geo[ex];
+                fx = E.afc[x].x;
+            }
         }
     }
-    float* dst = acc + kAccStride * R.p;
+    const int p = R.p;
+    const float m1 = same_group_shr<1>(p), m2 = same_group_shr<2>(p);
+    const float m4 = same_group_shr<4>(p), m8 = same_group_shr<8>(p);
+    const int pn = __builtin_amdgcn_update_dpp(-3, p, 0x101, 0xF, 0xF, false);  // lane + 1 of the row
+    const bool emit = p >= 0 && pn != p;
 #pragma unroll
-    for (int f = 0; f < 32; ++f) atomicAdd(dst + f, t[f]);
+    for (int f = 0; f < 32; ++f) {
+        float v = t[f];
+        v = fmaf(m1, row_shr<1>(v), v);
+        v = fmaf(m2, row_shr<2>(v), v);
+        v = fmaf(m4, row_shr<4>(v), v);
+        v = fmaf(m8, row_shr<8>(v), v);
+        t[f] = v;
+    }
+    if (emit) {
+        float* dst = acc + kAccStride * p;
+#pragma unroll
+        for (int f = 0; f < 32; ++f) atomicAdd(dst + f, t[f]);
+    }
 }
 
 // G[64..383] <- acc[10][33] (wave-cooperative; acc complete).
@@ -418,7 +480,7 @@ __device__ __forceinline__ void angular_store(const float* acc, float* G)
 // facc[3 * entry] (LDS).  Radial entries are owned by one lane each (plain
 // store); the angular pairs then add with LDS atomics.  The caller separates
 // the two phases with a barrier.
-__device__ void adjoint_radial(const Env& E, const float* g, float* facc)
+__device__ __forceinline__ void adjoint_radial(const Env& E, const float* g, float* facc)
 {
     const int lane = lane_id();
     const int nR = E.nR;
@@ -439,25 +501,39 @@ __device__ void adjoint_radial(const Env& E, const float* g, float* facc)
     }
 }
 
-__device__ void adjoint_angular(const Env& E, const float* g, float* facc)
+// Angular part of the adjoint.  A lane's run belongs to one element-pair
+// block, so its 32 values of dE/dG are read once; the force on the slowly
+// changing neighbour x is summed in registers and added when x changes, the
+// force on y with LDS atomics at every pair.
+__device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, float* facc)
 {
     const int lane = lane_id();
     PairRun R = lane_run(E, lane);
     if (R.p < 0) return;
-    const float* gb = g + 64 + 32 * R.p;
+    float gm[32];
+    const float4* gb = reinterpret_cast<const float4*>(g + 64 + 32 * R.p);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float4 v = gb[q];
+        gm[4 * q + 0] = v.x;
+        gm[4 * q + 1] = v.y;
+        gm[4 * q + 2] = v.z;
+        gm[4 * q + 3] = v.w;
+    }
+    int ex = E.ang[run_x(R)];
+    float4 gx = E.geo[ex];
+    float2 fx = E.afc[run_x(R)];
+    float ax = 0.f, ay = 0.f, az = 0.f;  // gradient of E_a with respect to x_x
     for (int it = 0; it < R.left; ++it) {
-        int j, k;
-        run_pair(R, j, k);
-        run_next(R);
-        const int ej = E.ang[j], ek = E.ang[k];
-        const float4 gj = E.geo[ej], gk = E.geo[ek];
-        const float2 fj = E.afc[j], fk = E.afc[k];
-        const float c = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
+        const int y = run_y(R);
+        const int ey = E.ang[y];
+        const float4 gy = E.geo[ey];
+        const float2 fy = E.afc[y];
+        const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
         const float cp = kCosScale * c;
-        const float sp = sqrtf(fmaxf(0.f, 1.f - cp * cp));
-        const float rbar = 0.5f * (gj.w + gk.w);
-        // P_n = sum_m g_mn B_m, Q_n = sum_m g_mn dB_m/drbar (g rows of the block
-        // read from LDS; lanes of one element pair read the same addresses)
+        const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - cp * cp));
+        const float rbar = 0.5f * (gx.w + gy.w);
+        // P_n = sum_m g_mn B_m, Q_n = sum_m g_mn dB_m/drbar
         float P[kNumSectors], Q[kNumSectors];
 #pragma unroll
         for (int n = 0; n < kNumSectors; ++n) {
@@ -469,17 +545,14 @@ __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
             const float x = rbar - (0.9f + 0.65f * (float)m);
             const float Bm = __expf(-kEtaAng * x * x);
             const float dBm = -2.f * kEtaAng * x * Bm;
-            const float4 g0 = *reinterpret_cast<const float4*>(gb + 8 * m);
-            const float4 g1 = *reinterpret_cast<const float4*>(gb + 8 * m + 4);
-            const float gm[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
 #pragma unroll
             for (int n = 0; n < kNumSectors; ++n) {
-                P[n] += gm[n] * Bm;
-                Q[n] += gm[n] * dBm;
+                P[n] += gm[8 * m + n] * Bm;
+                Q[n] += gm[8 * m + n] * dBm;
             }
         }
         float Et = 0.f, dEdcp = 0.f, dEdrb = 0.f;
-        const float inv_sp = 1.f / sp;
+        const float inv_sp = __builtin_amdgcn_rcpf(sp);  // sp >= sqrt(1 - 0.95^2)
 #pragma unroll
         for (int n = 0; n < kNumSectors; ++n) {
             const float ct = kSecCos[n], st = kSecSin[n];
@@ -492,31 +565,41 @@ __device__ void adjoint_angular(const Env& E, const float* g, float* facc)
             dEdcp += dA * P[n];
             dEdrb += A * Q[n];
         }
-        // E_t = w * sum_n A_n P_n with w = 2^-31 fc_j fc_k
+        // E_t = w * sum_n A_n P_n with w = 2^-31 fc_x fc_y
         const float pre = kTwoPowM31;
-        const float ff = fj.x * fk.x;
+        const float ff = fx.x * fy.x;
         const float dEdc = pre * ff * kCosScale * dEdcp;
-        const float dEdrj = pre * (Et * fj.y * fk.x + 0.5f * ff * dEdrb);
-        const float dEdrk = pre * (Et * fj.x * fk.y + 0.5f * ff * dEdrb);
-        const float ij = 1.f / gj.w, ik = 1.f / gk.w;
-        // gradient of E_a with respect to x_j and x_k; the force is its negative
-        const float gjx = dEdrj * gj.x + dEdc * (gk.x - c * gj.x) * ij;
-        const float gjy = dEdrj * gj.y + dEdc * (gk.y - c * gj.y) * ij;
-        const float gjz = dEdrj * gj.z + dEdc * (gk.z - c * gj.z) * ij;
-        const float gkx = dEdrk * gk.x + dEdc * (gj.x - c * gk.x) * ik;
-        const float gky = dEdrk * gk.y + dEdc * (gj.y - c * gk.y) * ik;
-        const float gkz = dEdrk * gk.z + dEdc * (gj.z - c * gk.z) * ik;
-        atomicAdd(&facc[3 * ej + 0], -gjx);
-        atomicAdd(&facc[3 * ej + 1], -gjy);
-        atomicAdd(&facc[3 * ej + 2], -gjz);
-        atomicAdd(&facc[3 * ek + 0], -gkx);
-        atomicAdd(&facc[3 * ek + 1], -gky);
-        atomicAdd(&facc[3 * ek + 2], -gkz);
+        const float dEdrx = pre * (Et * fx.y * fy.x + 0.5f * ff * dEdrb);
+        const float dEdry = pre * (Et * fx.x * fy.y + 0.5f * ff * dEdrb);
+        const float ix = __builtin_amdgcn_rcpf(gx.w), iy = __builtin_amdgcn_rcpf(gy.w);
+        // gradient of E_a with respect to x_x and x_y; the force is its negative
+        ax += dEdrx * gx.x + dEdc * (gy.x - c * gx.x) * ix;
+        ay += dEdrx * gx.y + dEdc * (gy.y - c * gx.y) * ix;
+        az += dEdrx * gx.z + dEdc * (gy.z - c * gx.z) * ix;
+        const float gyx = dEdry * gy.x + dEdc * (gx.x - c * gy.x) * iy;
+        const float gyy = dEdry * gy.y + dEdc * (gx.y - c * gy.y) * iy;
+        const float gyz = dEdry * gy.z + dEdc * (gx.z - c * gy.z) * iy;
+        atomicAdd(&facc[3 * ey + 0], -gyx);
+        atomicAdd(&facc[3 * ey + 1], -gyy);
+        atomicAdd(&facc[3 * ey + 2], -gyz);
+        if (run_next(R) && it + 1 < R.left) {
+            atomicAdd(&facc[3 * ex + 0], -ax);
+            atomicAdd(&facc[3 * ex + 1], -ay);
+            atomicAdd(&facc[3 * ex + 2], -az);
+            ax = ay = az = 0.f;
+            const int x = run_x(R);
+            ex = E.ang[x];
+            gx = E.geo[ex];
+            fx = E.afc[x];
+        }
     }
+    atomicAdd(&facc[3 * ex + 0], -ax);
+    atomicAdd(&facc[3 * ex + 1], -ay);
+    atomicAdd(&facc[3 * ex + 2], -az);
 }
 
 // Writes the per-slot forces of atom a to HBM (zero for slots beyond 5.2 A).
-__device__ void store_slot_forces(const Sys& S, int a, const Env& E, const float* facc)
+__device__ __forceinline__ void store_slot_forces(const Sys& S, int a, const Env& E, const float* facc)
 {
     const int lane = lane_id();
     const size_t base = (size_t)a * S.cap;
@@ -590,7 +673,7 @@ struct MlpF32Smem {
 // FP32 network forward + input gradient on VALU.  G: [T][kLdG] fp32 in LDS,
 // replaced by dE/dG when GRAD.  E[T] receives the atom energies.
 template <int T, bool GRAD>
-__device__ void mlp_f32(const float* __restrict__ w, float* G, MlpF32Smem<T>& sm, float* E, int tid, int nthr)
+__device__ __forceinline__ void mlp_f32(const float* __restrict__ w, float* G, MlpF32Smem<T>& sm, float* E, int tid, int nthr)
 {
     using L = W32Layout;
     dense_f32<T, kNumFeat, kH1, 0>(G, kLdG, w + L::Wt1, w + L::B1, sm.h1, kLdF1, sm.d1, kLdF1, tid, nthr);
@@ -639,6 +722,23 @@ struct MlpMfmaSmem {
     float ep[8 * 16];         // output-layer partial sums per (m tile, atom)
 };
 
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+// Four consecutive activations (idx a multiple of 4): one 8-byte store per
+// array.
+template <bool SPLIT>
+__device__ __forceinline__ void put_act4(__bf16* hi, __bf16* lo, int idx, const floatx4& v)
+{
+    bf16x4 h, l;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h[i] = (__bf16)v[i];
+        if constexpr (SPLIT) l[i] = (__bf16)(v[i] - (float)h[i]);
+    }
+    *reinterpret_cast<bf16x4*>(hi + idx) = h;
+    if constexpr (SPLIT) *reinterpret_cast<bf16x4*>(lo + idx) = l;
+}
+
 template <bool SPLIT>
 __device__ __forceinline__ void put_act(__bf16* hi, __bf16* lo, int idx, float v)
 {
@@ -678,7 +778,9 @@ template <int T, int KT, bool SPLIT>
 __device__ __forceinline__ floatx4 mfma_tile(const bf16x8* __restrict__ fhi, const bf16x8* __restrict__ flo,
                                              const __bf16* bhi, const __bf16* blo, int ld, int lane)
 {
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    // independent accumulators (hi*hi / hi*lo / lo*hi, or even / odd k
+    // steps) keep several MFMAs in flight instead of one dependent chain
+    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0;
     const int col = lane & 15, kq = (lane >> 4) * 8;
     const bool live = col < T;
     const bf16x8 zero = {};
@@ -688,15 +790,22 @@ __device__ __forceinline__ floatx4 mfma_tile(const bf16x8* __restrict__ fhi, con
         const bf16x8 a = fhi[kt * 64 + lane];
         bf16x8 bh = *reinterpret_cast<const bf16x8*>(bhi + off + kt * 32);
         if (!live) bh = zero;
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
         if constexpr (SPLIT) {
             bf16x8 bl = *reinterpret_cast<const bf16x8*>(blo + off + kt * 32);
             if (!live) bl = zero;
             const bf16x8 al = flo[kt * 64 + lane];
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc2, 0, 0, 0);
+        } else if (kt & 1) {
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc1, 0, 0, 0);
+        } else {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc0, 0, 0, 0);
         }
     }
+    floatx4 acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = acc0[i] + (acc1[i] + acc2[i]);
     return acc;
 }
 
@@ -706,7 +815,7 @@ __device__ __forceinline__ floatx4 mfma_tile(const bf16x8* __restrict__ fhi, con
 // fr points at the element's hi fragments; its lo fragments follow after
 // FragLayout::Count fragments.
 template <int T, bool SPLIT, bool GRAD>
-__device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__ fr, float* G,
+__device__ __forceinline__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__ fr, float* G,
                          MlpMfmaSmem<T, SPLIT>& sm, float* E, int tid, int nthr)
 {
     using L = W32Layout;
@@ -723,13 +832,17 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
         const int f = (F::F1 + mt * 12) * 64;
         const floatx4 acc = mfma_tile<T, 12, SPLIT>(fr + f, lo + f, ghi, glo, kLdG, lane);
         if (live) {
+            const int o = mt * 16 + rq;
+            const float4 b = *reinterpret_cast<const float4*>(w + L::B1 + o);
+            const floatx4 z = {acc[0] + b.x, acc[1] + b.y, acc[2] + b.z, acc[3] + b.w};
+            floatx4 h, d;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int o = mt * 16 + rq + i;
-                const float z = acc[i] + w[L::B1 + o];
-                put_act<SPLIT>(sm.h1[0], sm.h1[LO], col * kLd1 + o, celu_f(z));
-                sm.d1[col * kLdF1 + o] = celu_d(z);
+                h[i] = celu_f(z[i]);
+                d[i] = celu_d(z[i]);
             }
+            put_act4<SPLIT>(sm.h1[0], sm.h1[LO], col * kLd1 + o, h);
+            *reinterpret_cast<floatx4*>(sm.d1 + col * kLdF1 + o) = d;
         }
     }
     __syncthreads();
@@ -738,13 +851,17 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
         const int f = (F::F2 + mt * 5) * 64;
         const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1[0], sm.h1[LO], kLd1, lane);
         if (live) {
+            const int o = mt * 16 + rq;
+            const float4 b = *reinterpret_cast<const float4*>(w + L::B2 + o);
+            const floatx4 z = {acc[0] + b.x, acc[1] + b.y, acc[2] + b.z, acc[3] + b.w};
+            floatx4 h, d;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int o = mt * 16 + rq + i;
-                const float z = acc[i] + w[L::B2 + o];
-                put_act<SPLIT>(sm.h2[0], sm.h2[LO], col * kLd2 + o, celu_f(z));
-                sm.d2[col * kLdF2 + o] = celu_d(z);
+                h[i] = celu_f(z[i]);
+                d[i] = celu_d(z[i]);
             }
+            put_act4<SPLIT>(sm.h2[0], sm.h2[LO], col * kLd2 + o, h);
+            *reinterpret_cast<floatx4*>(sm.d2 + col * kLdF2 + o) = d;
         }
     }
     __syncthreads();
@@ -753,14 +870,18 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
         const int f = (F::F3 + mt * 4) * 64;
         const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2[0], sm.h2[LO], kLd2, lane);
         float part = 0.f;
+        const int o = mt * 16 + rq;
+        const float4 b = *reinterpret_cast<const float4*>(w + L::B3 + o);
+        const float4 w4 = *reinterpret_cast<const float4*>(w + L::W4 + o);
+        const floatx4 z = {acc[0] + b.x, acc[1] + b.y, acc[2] + b.z, acc[3] + b.w};
+        const floatx4 w4v = {w4.x, w4.y, w4.z, w4.w};
+        floatx4 d3;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int o = mt * 16 + rq + i;
-            const float z = acc[i] + w[L::B3 + o];
-            const float w4 = w[L::W4 + o];
-            part += w4 * celu_f(z);
-            if (live) put_act<SPLIT>(sm.h3[0], sm.h3[LO], col * kLd3 + o, celu_d(z) * w4);
+            part += w4v[i] * celu_f(z[i]);
+            d3[i] = celu_d(z[i]) * w4v[i];
         }
+        if (live) put_act4<SPLIT>(sm.h3[0], sm.h3[LO], col * kLd3 + o, d3);
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
         if (lane < 16) sm.ep[mt * 16 + lane] = part;
@@ -777,11 +898,10 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
         const int f = (F::B3 + mt * 3) * 64;
         const floatx4 acc = mfma_tile<T, 3, SPLIT>(fr + f, lo + f, sm.h3[0], sm.h3[LO], kLd3, lane);
         if (live) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = mt * 16 + rq + i;
-                put_act<SPLIT>(sm.h2[0], sm.h2[LO], col * kLd2 + o, acc[i] * sm.d2[col * kLdF2 + o]);
-            }
+            const int o = mt * 16 + rq;
+            const floatx4 d = *reinterpret_cast<const floatx4*>(sm.d2 + col * kLdF2 + o);
+            const floatx4 v = {acc[0] * d[0], acc[1] * d[1], acc[2] * d[2], acc[3] * d[3]};
+            put_act4<SPLIT>(sm.h2[0], sm.h2[LO], col * kLd2 + o, v);
         }
     }
     __syncthreads();
@@ -790,11 +910,10 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
         const int f = (F::B2 + mt * 4) * 64;
         const floatx4 acc = mfma_tile<T, 4, SPLIT>(fr + f, lo + f, sm.h2[0], sm.h2[LO], kLd2, lane);
         if (live) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = mt * 16 + rq + i;
-                put_act<SPLIT>(sm.h1[0], sm.h1[LO], col * kLd1 + o, acc[i] * sm.d1[col * kLdF1 + o]);
-            }
+            const int o = mt * 16 + rq;
+            const floatx4 d = *reinterpret_cast<const floatx4*>(sm.d1 + col * kLdF1 + o);
+            const floatx4 v = {acc[0] * d[0], acc[1] * d[1], acc[2] * d[2], acc[3] * d[3]};
+            put_act4<SPLIT>(sm.h1[0], sm.h1[LO], col * kLd1 + o, v);
         }
     }
     __syncthreads();
@@ -802,10 +921,7 @@ __device__ void mlp_mfma(const float* __restrict__ w, const bf16x8* __restrict__
     for (int mt = wave; mt < 24; mt += nw) {
         const int f = (F::B1 + mt * 5) * 64;
         const floatx4 acc = mfma_tile<T, 5, SPLIT>(fr + f, lo + f, sm.h1[0], sm.h1[LO], kLd1, lane);
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) G[col * kLdG + mt * 16 + rq + i] = acc[i];
-        }
+        if (live) *reinterpret_cast<floatx4*>(G + col * kLdG + mt * 16 + rq) = acc;
     }
     __syncthreads();
 }
@@ -833,7 +949,7 @@ struct MlpFp8Smem {
 // src [T][ld] (first K columns) -> E4M3 rows of q scaled by 448 / amax;
 // returns the inverse scale.  Workgroup-wide.
 template <int T>
-__device__ float quantize_tile(const float* src, int ld, int K, unsigned char* q, unsigned* amax, int tid, int nthr)
+__device__ __forceinline__ float quantize_tile(const float* src, int ld, int K, unsigned char* q, unsigned* amax, int tid, int nthr)
 {
     if (tid == 0) *amax = 0u;
     __syncthreads();
@@ -859,7 +975,7 @@ __device__ float quantize_tile(const float* src, int ld, int K, unsigned char* q
 template <int T, int KT>
 __device__ __forceinline__ floatx4 mfma_tile_fp8(const long* __restrict__ frag, const unsigned char* q, int lane)
 {
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
     const int col = lane & 15, kq = (lane >> 4) * 8;
     const bool live = col < T;
     const unsigned char* row = q + (live ? col : 0) * kLdQ + kq;
@@ -868,15 +984,21 @@ __device__ __forceinline__ floatx4 mfma_tile_fp8(const long* __restrict__ frag, 
         const long a = frag[kt * 64 + lane];
         long b = *reinterpret_cast<const long*>(row + kt * 32);
         if (!live) b = 0;
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc, 0, 0, 0);
+        if (kt & 1)
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc1, 0, 0, 0);
+        else
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc0, 0, 0, 0);
     }
+    floatx4 acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = acc0[i] + acc1[i];
     return acc;
 }
 
 // FP8 network forward + input gradient.  G: fp32 [T][kLdG], replaced by
 // dE/dG when GRAD.  ws: inverse weight scales of layers F1 F2 F3 B3 B2 B1.
 template <int T, bool GRAD>
-__device__ void mlp_fp8(const float* __restrict__ w, const long* __restrict__ fr, const float* __restrict__ ws,
+__device__ __forceinline__ void mlp_fp8(const float* __restrict__ w, const long* __restrict__ fr, const float* __restrict__ ws,
                         float* G, MlpFp8Smem<T>& sm, float* E, int tid, int nthr)
 {
     using L = W32Layout;

@@ -38,6 +38,7 @@ constexpr int kRadMax = 160;  // radial entries per atom held in LDS
 constexpr int kAngMax = 96;   // angular entries per atom held in LDS
 constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits)
 constexpr int kRing = 4096;   // energy log ring (steps)
+constexpr int kXcds = 8;     // accelerator complex dies; workgroups go round-robin
 
 // Per-element FP32 weight block (floats).  Forward dense layers read the
 // transposed matrices ([in][out], coalesced over outputs), the backward ones
