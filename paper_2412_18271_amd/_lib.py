@@ -57,6 +57,20 @@ class NNPError(RuntimeError):
 _lib = None
 
 
+def _init_torch_first():
+    """PyTorch-ROCm wheels carry their own copy of the HIP runtime, so a
+    process that uses both PyTorch and this library holds two.  PyTorch's
+    must be initialised first (in the other order PyTorch finds no device),
+    so it is brought up here, before the library's runtime is loaded,
+    whenever PyTorch is importable."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load():
     """Loads libnnp_hip.so (raises if it is missing)."""
     global _lib
@@ -65,6 +79,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("HIP library %s is not built; run `python -m paper_2412_18271_amd.build`"
                           % LIB_PATH)
+    _init_torch_first()
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, d, i32, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64

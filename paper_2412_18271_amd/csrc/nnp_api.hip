@@ -46,6 +46,7 @@ struct nnp_context {
     std::string err;
     // configuration
     int n = 0, nmol = 0, cap = 160, T = 16;
+    bool T_auto = false;  // atoms per tile chosen at layout
     nnp_dtype dtype = NNP_MLP_FP32;
     nnp_path path = NNP_PATH_FUSED;
     int rebuild_every = 20;
@@ -158,6 +159,8 @@ nnp_status check_positions(nnp_context* c, const double* pos)
 // (workgroup b runs on XCD b mod 8), so the table is permuted to give each XCD
 // one contiguous run of tiles: an XCD then meets one or two elements and its
 // L2 holds only their weight fragments.
+bool fused_tile_ok(int T) { return T == 4 || T == 8 || T == 10 || T == 16; }
+
 std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
 {
     std::vector<int4> seq;
@@ -230,6 +233,13 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     }
     std::vector<int> elem(n);
     for (int k = 0; k < n; ++k) elem[k] = (int)p4[k].w;
+    if (c->T_auto) {
+        // one workgroup per CU when 10 atoms per tile make that possible and 8
+        // would leave some CUs with two (the second one runs after the first)
+        int dev = 0, ncu = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        c->T = (make_tiles(elem, 8).size() > (size_t)ncu && make_tiles(elem, 10).size() <= (size_t)ncu) ? 10 : 8;
+    }
     const std::vector<int4> tiles = make_tiles(elem, c->T);
     std::vector<int> perm_dev(c->perm.begin(), c->perm.end());
     Sys& S = c->S;
@@ -559,8 +569,8 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
     if (p->rebuild_every < 1) return msg = "rebuild_every must be >= 1", NNP_ERR_ARG;
     if (!(p->skin >= 0.0) || !std::isfinite(p->skin) || p->skin > 5.0) return msg = "skin must be in [0, 5] A", NNP_ERR_ARG;
     if (p->max_neighbors < 0 || p->max_neighbors > kCapMax) return msg = "max_neighbors must be in [0, 256]", NNP_ERR_ARG;
-    if (p->path == NNP_PATH_FUSED && p->atoms_per_tile != 0 && p->atoms_per_tile != 4 && p->atoms_per_tile != 8)
-        return msg = "atoms_per_tile of the fused path must be 0, 4 or 8", NNP_ERR_ARG;
+    if (p->path == NNP_PATH_FUSED && p->atoms_per_tile != 0 && !fused_tile_ok(p->atoms_per_tile))
+        return msg = "atoms_per_tile of the fused path must be 0, 4, 8, 10 or 16", NNP_ERR_ARG;
     if (p->path == NNP_PATH_PLAIN && p->atoms_per_tile != 0 && p->atoms_per_tile != 8 && p->atoms_per_tile != 16)
         return msg = "atoms_per_tile of the plain path must be 0, 8 or 16", NNP_ERR_ARG;
     return NNP_OK;
@@ -582,6 +592,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     c->nmol = p->n_molecules;
     c->cap = p->max_neighbors ? p->max_neighbors : 192;
     c->T = p->atoms_per_tile ? p->atoms_per_tile : (p->path == NNP_PATH_FUSED ? 8 : 16);
+    c->T_auto = p->atoms_per_tile == 0 && p->path == NNP_PATH_FUSED;
     c->dtype = p->mlp_dtype;
     c->path = p->path;
     c->rebuild_every = p->rebuild_every;
@@ -632,8 +643,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(tiles, const int4*, n)
     ALLOC(nbr, int*, n * cap)
     ALLOC(ncnt, int*, n)
-    ALLOC(rev, int*, n * cap)
-    ALLOC(fslot, float4*, n * cap)
+    ALLOC(facc, unsigned long long*, 4 * (size_t)n)
     ALLOC(Ei, float*, n)
     ALLOC(Uring, double*, (size_t)kRing * nm)
     ALLOC(Kring, double*, (size_t)kRing * nm)
@@ -1043,6 +1053,9 @@ nnp_status nnp_time_kernels(nnp_context* c, int32_t reps, double* ms)
     (void)hipEventDestroy(e2);
     ms[0] = a / reps;
     ms[1] = b / reps;
+    // the timed evaluations summed their forces without a gather in between:
+    // one complete evaluation leaves the forces and energies consistent
+    HIP_TRY(c, enqueue_compute(c, true));
     c->forces_current = true;
     c->kick_pending = false;
     return check_device_flags(c);
@@ -1107,10 +1120,14 @@ nnp_status nnp_autotune(nnp_context* c, const char* cache_path)
             const size_t p = line.find("\"atoms_per_tile\": ");
             if (p == std::string::npos) continue;
             const int T = std::atoi(line.c_str() + p + 18);
-            if (T == 4 || T == 8 || T == 16) return retile(c, T);
+            if (c->path == NNP_PATH_FUSED ? fused_tile_ok(T) : (T == 8 || T == 16)) return retile(c, T);
         }
     }
-    const int cand[2] = {c->path == NNP_PATH_FUSED ? 4 : 8, c->path == NNP_PATH_FUSED ? 8 : 16};
+    std::vector<int> cand;
+    if (c->path == NNP_PATH_FUSED)
+        cand = {4, 8, 10, 16};
+    else
+        cand = {8, 16};
     double best = 1e300;
     int bestT = c->T;
     hipEvent_t e0, e1;

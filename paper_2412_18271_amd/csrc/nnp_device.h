@@ -598,17 +598,49 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
     atomicAdd(&facc[3 * ex + 2], -az);
 }
 
-// Writes the per-slot forces of atom a to HBM (zero for slots beyond 5.2 A).
-__device__ __forceinline__ void store_slot_forces(const Sys& S, int a, const Env& E, const float* facc)
+// Adds the forces of E_a to the fixed-point accumulators: each neighbour
+// within 5.2 A receives its force (LDS facc[3 * entry]), atom a receives
+// minus their sum (translation invariance of E_a).  Components are rounded
+// to multiples of 2^-32 eV/A once per neighbour; the integer sums do not
+// depend on the order in which workgroups add.  A non-finite component or
+// one beyond kFixMax sets the non-finite flag instead of being added.
+__device__ __forceinline__ void accumulate_forces(const Sys& S, int a, const Env& E, const float* facc)
 {
     const int lane = lane_id();
     const size_t base = (size_t)a * S.cap;
-    for (int s = lane; s < E.nS; s += 64) {
-        const int e = E.smap[s];
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (e != kNoEntry) v = make_float4(facc[3 * e], facc[3 * e + 1], facc[3 * e + 2], 0.f);
-        S.fslot[base + s] = v;
+    long long sx = 0, sy = 0, sz = 0;
+    bool bad = false;
+    for (int e = lane; e < E.nR; e += 64) {
+        const float fx = facc[3 * e], fy = facc[3 * e + 1], fz = facc[3 * e + 2];
+        if (!(fabsf(fx) < kFixMax && fabsf(fy) < kFixMax && fabsf(fz) < kFixMax)) {
+            bad = true;
+            continue;
+        }
+        const int j = S.nbr[base + (E.info[e] >> 2)];
+        const long long qx = __double2ll_rn((double)fx * kFixScale);
+        const long long qy = __double2ll_rn((double)fy * kFixScale);
+        const long long qz = __double2ll_rn((double)fz * kFixScale);
+        unsigned long long* fj = S.facc + 4 * (size_t)j;
+        atomicAdd(fj + 0, (unsigned long long)qx);
+        atomicAdd(fj + 1, (unsigned long long)qy);
+        atomicAdd(fj + 2, (unsigned long long)qz);
+        sx += qx;
+        sy += qy;
+        sz += qz;
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off);
+        sy += __shfl_xor(sy, off);
+        sz += __shfl_xor(sz, off);
+    }
+    if (lane == 0) {
+        unsigned long long* fa = S.facc + 4 * (size_t)a;
+        atomicAdd(fa + 0, (unsigned long long)(-sx));
+        atomicAdd(fa + 1, (unsigned long long)(-sy));
+        atomicAdd(fa + 2, (unsigned long long)(-sz));
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&S.st->nonfinite, 1);
 }
 
 // ------------------------------------------------------------------------
@@ -640,7 +672,9 @@ __device__ __forceinline__ void dense_f32(const float* in, int ldi, const float*
             const float w2 = Wm[(k + 2) * M + o], w3 = Wm[(k + 3) * M + o];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const float4 x = *reinterpret_cast<const float4*>(in + (4 * ag + t) * ldi + k);
+                // rows past T (T not a multiple of 4) re-read row T - 1; discarded below
+                const int row = 4 * ag + t < T ? 4 * ag + t : T - 1;
+                const float4 x = *reinterpret_cast<const float4*>(in + row * ldi + k);
                 acc[t] += x.x * w0 + x.y * w1 + x.z * w2 + x.w * w3;
             }
         }

@@ -9,8 +9,10 @@
 //   frc    double4[n]    gathered FP64 forces (eV/A)
 //   ref    float4[n]     positions at the last pair-list rebuild
 //   nbr    int[n][cap]   pair list (cutoff 5.2 + skin), ascending internal index
-//   rev    int[n][cap]   position of atom a in the list of its neighbour j
-//   fslot  float4[n][cap] force on neighbour nbr[a][s] due to E_a (eV/A)
+//   facc   int64[n][4]   force accumulators of the running evaluation, fixed
+//                        point with 2^-32 eV/A resolution (x, y, z, unused);
+//                        integer addition makes the sum independent of the
+//                        order of the atomic adds
 //   Ei     float[n]      per-atom energies of the last evaluation
 #pragma once
 
@@ -26,6 +28,8 @@ constexpr int kNumSectors = 8;
 constexpr int kNumFeat = 384;   // 4 * 16 radial + 10 * 32 angular
 constexpr int kH1 = 160, kH2 = 128, kH3 = 96;
 
+constexpr double kFixScale = 4294967296.0;  // fixed-point force units per eV/A (2^32)
+constexpr float kFixMax = 1073741824.0f;    // largest accepted |force component| (2^30 eV/A)
 constexpr float kCutRad = 5.2f;
 constexpr float kCutAng = 3.5f;
 constexpr float kEtaRad = 16.0f;
@@ -114,8 +118,7 @@ struct Sys {
     const int4* tiles;   // {first atom, count, element, 0}
     int* nbr;
     int* ncnt;
-    int* rev;
-    float4* fslot;
+    unsigned long long* facc;  // [n][4] fixed-point forces, zero between evaluations
     float* Ei;
     double* Uring;  // [kRing][nmol]
     double* Kring;

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
         __syncthreads();
         if (act) adjoint_angular(E, Grow, fa);
         __syncthreads();
-        if (act) store_slot_forces(S, a, E, fa);
+        if (act) accumulate_forces(S, a, E, fa);
     }
 }
 
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_adjoint(Sys S)
     __syncthreads();
     if (a < S.n) adjoint_angular(env[wave], gr, fa);
     __syncthreads();
-    if (a < S.n) store_slot_forces(S, a, env[wave], fa);
+    if (a < S.n) accumulate_forces(S, a, env[wave], fa);
 }
 
 // --------------------------------------------------- gather + integrate ---
@@ -196,143 +196,85 @@ __device__ __forceinline__ double atomic_read(double* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Completes an evaluation: converts the fixed-point force sums to FP64 (and
+// clears them for the next evaluation), integrates, reduces the per-molecule
+// energies and, in the last block to finish, advances the step state.
 // mode 0: evaluation only (forces, energies; no integration, step unchanged)
 // mode 1: second half kick (completes a step), step += 1
 // mode 2: as 1, then the first half kick and drift of the next step
-// One wave per atom (lanes over its pair-list slots), 16 atoms per block.
-constexpr int kGatherAtoms = 16;
+// One thread per atom.
+constexpr int kGatherThreads = 256;
 
-__global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, double dt, int mode, int forces)
+__global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, double dt, int mode, int forces)
 {
-    __shared__ double sE[kGatherAtoms], sK[kGatherAtoms];
-    __shared__ int sM[kGatherAtoms];
     __shared__ int last;
-    const int tid = threadIdx.x, lane = tid & 63, la = tid >> 6;
-    const int a = blockIdx.x * kGatherAtoms + la;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int a = blockIdx.x * kGatherThreads + tid;
     StepState* st = S.st;
-    const bool rb = rebuild_due(st, S.rebuild_every);
-    const int nstep = st->step;
-    // per-atom integration inputs, issued before the gather so their latency
-    // overlaps it
-    double4 v = make_double4(0, 0, 0, 0), p = make_double4(0, 0, 0, 0);
-    double ki = 0.0, mass = 0.0, e = 0.0;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // step state as the evaluation saw it; only the last block writes it
+    const int nstep = st->step, age = st->age, valid = st->lists_valid;
+    const bool rb = !valid || st->viol[nstep & 1] || age >= S.rebuild_every;
+    double e = 0.0, k = 0.0;
     int mol = -1;
-    if (lane == 0 && a < S.n) {
-        v = S.vel[a];
-        p = S.pos[a];
-        ki = S.kinv[a];
-        mass = S.mass[a];
+    bool moved = false, bad = false;
+    if (a < S.n) {
+        unsigned long long* fa = S.facc + 4 * (size_t)a;
+        const unsigned long long qx = fa[0], qy = fa[1], qz = fa[2];
+        fa[0] = 0ull;
+        fa[1] = 0ull;
+        fa[2] = 0ull;
+        const double fx = (double)(long long)qx * (1.0 / kFixScale);
+        const double fy = (double)(long long)qy * (1.0 / kFixScale);
+        const double fz = (double)(long long)qz * (1.0 / kFixScale);
+        double4 v = S.vel[a];
+        const double ki = S.kinv[a];
         e = (double)S.Ei[a];
-        r0 = S.ref[a];
         mol = S.mol[a];
+        if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
+        if (mode >= 1) {
+            v.x += 0.5 * dt * ki * fx;
+            v.y += 0.5 * dt * ki * fy;
+            v.z += 0.5 * dt * ki * fz;
+        }
+        k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
+        if (mode == 2) {
+            double4 p = S.pos[a];
+            const float4 r0 = S.ref[a];
+            v.x += 0.5 * dt * ki * fx;
+            v.y += 0.5 * dt * ki * fy;
+            v.z += 0.5 * dt * ki * fz;
+            p.x += dt * v.x;
+            p.y += dt * v.y;
+            p.z += dt * v.z;
+            S.pos[a] = p;
+            const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
+            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
+        }
+        if (mode >= 1) S.vel[a] = v;
+        bad = !isfinite(e);
     }
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    // without forces the slot loop still runs on rebuild steps: the reverse
-    // slot indices of the new pair list are recorded here
-    if (a < S.n && (forces || rb)) {
-        // a lane holds up to kCapMax / 64 slots; all their loads are issued
-        // together (nbr, rev, own slot force), then the reverse slot forces
-        constexpr int U = kCapMax / 64;
-        const int cnt = S.ncnt[a];
-        const size_t base = (size_t)a * S.cap;
-        int jv[U], rv[U];
-        float4 fo[U];
+    if (__ballot(moved) != 0ull && lane == 0) atomicOr(&st->viol[(nstep + 1) & 1], 1);
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&st->nonfinite, 1);
+    // per wave, one pair of FP64 atomics per molecule present
+    unsigned long long todo = __ballot(mol >= 0);
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        const int m = __shfl(mol, src);
+        const bool mine = mol == m;
+        double es = mine ? e : 0.0, ks = mine ? k : 0.0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int s = lane + 64 * u;
-            jv[u] = -1;
-            if (s < cnt) {
-                jv[u] = S.nbr[base + s];
-                rv[u] = rb ? 0 : S.rev[base + s];
-                fo[u] = S.fslot[base + s];
-            }
+        for (int off = 32; off > 0; off >>= 1) {
+            es += __shfl_xor(es, off);
+            ks += __shfl_xor(ks, off);
         }
-        if (rb) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (jv[u] < 0) continue;
-                const int j = jv[u];
-                const int* lj = S.nbr + (size_t)j * S.cap;
-                int lo = 0, hi = S.ncnt[j] - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (lj[mid] < a)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                rv[u] = lo;
-                S.rev[base + lane + 64 * u] = lo;
-            }
+        if (lane == src) {
+            atomicAdd(&S.Eacc[m], es);
+            atomicAdd(&S.Kacc[m], ks);
         }
-        float4 fi[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (jv[u] >= 0) fi[u] = S.fslot[(size_t)jv[u] * S.cap + rv[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (jv[u] < 0) continue;
-            fx += (double)fi[u].x - (double)fo[u].x;
-            fy += (double)fi[u].y - (double)fo[u].y;
-            fz += (double)fi[u].z - (double)fo[u].z;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        fx += __shfl_xor(fx, off);
-        fy += __shfl_xor(fy, off);
-        fz += __shfl_xor(fz, off);
-    }
-    if (lane == 0) {
-        if (a < S.n) {
-            if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
-            if (mode >= 1) {
-                v.x += 0.5 * dt * ki * fx;
-                v.y += 0.5 * dt * ki * fy;
-                v.z += 0.5 * dt * ki * fz;
-            }
-            const double k = 0.5 * mass * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
-            if (mode == 2) {
-                v.x += 0.5 * dt * ki * fx;
-                v.y += 0.5 * dt * ki * fy;
-                v.z += 0.5 * dt * ki * fz;
-                p.x += dt * v.x;
-                p.y += dt * v.y;
-                p.z += dt * v.z;
-                S.pos[a] = p;
-                const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
-                if (dx * dx + dy * dy + dz * dz > S.half_skin2) atomicOr(&st->viol[(nstep + 1) & 1], 1);
-            }
-            if (mode >= 1) S.vel[a] = v;
-            if (!isfinite(fx + fy + fz + e)) atomicOr(&st->nonfinite, 1);
-            sE[la] = e;
-            sK[la] = k;
-            sM[la] = mol;
-        } else {
-            sE[la] = 0.0;
-            sK[la] = 0.0;
-            sM[la] = -1;
-        }
+        todo &= ~__ballot(mine);
     }
     __syncthreads();
     if (tid == 0) {
-        int i = 0;
-        while (i < kGatherAtoms) {
-            const int m = sM[i];
-            if (m < 0) {
-                ++i;
-                continue;
-            }
-            double e = 0.0, k = 0.0;
-            while (i < kGatherAtoms && sM[i] == m) {
-                e += sE[i];
-                k += sK[i];
-                ++i;
-            }
-            atomicAdd(&S.Eacc[m], e);
-            atomicAdd(&S.Kacc[m], k);
-        }
         __threadfence();
         const unsigned prev = atomicAdd(&st->done, 1u);
         last = prev == gridDim.x - 1;
@@ -345,25 +287,25 @@ __global__ __launch_bounds__(64 * kGatherAtoms) void k_gather_integrate(Sys S, d
     const int eval_index = mode >= 1 ? nstep + 1 : nstep;
     const int slot = eval_index % kRing;
     for (int m = tid; m < S.nmol; m += blockDim.x) {
-        const double e = atomic_read(&S.Eacc[m]);
-        const double k = atomic_read(&S.Kacc[m]);
-        S.Uring[(size_t)slot * S.nmol + m] = e;
-        S.Kring[(size_t)slot * S.nmol + m] = k;
-        S.Ecur[m] = e;
-        S.Kcur[m] = k;
-        if (!isfinite(e)) atomicOr(&st->nonfinite, 1);
+        const double em = atomic_read(&S.Eacc[m]);
+        const double km = atomic_read(&S.Kacc[m]);
+        S.Uring[(size_t)slot * S.nmol + m] = em;
+        S.Kring[(size_t)slot * S.nmol + m] = km;
+        S.Ecur[m] = em;
+        S.Kcur[m] = km;
+        if (!isfinite(em)) atomicOr(&st->nonfinite, 1);
         __hip_atomic_store(&S.Eacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&S.Kacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid == 0) {
-        st->n_eval += 1;
+        // new values from the state read at entry: no read-modify-write
+        atomicAdd((unsigned long long*)&st->n_eval, 1ull);
         if (rb) {
-            st->n_rebuild += 1;
-            if (st->lists_valid && st->age < S.rebuild_every) st->n_forced += 1;
-            st->age = 0;
+            atomicAdd((unsigned long long*)&st->n_rebuild, 1ull);
+            if (valid && age < S.rebuild_every) atomicAdd((unsigned long long*)&st->n_forced, 1ull);
             st->lists_valid = 1;
         }
-        st->age += 1;
+        st->age = rb ? 1 : age + 1;
         st->viol[nstep & 1] = 0;
         st->last_slot = eval_index;
         if (mode >= 1) st->step = nstep + 1;
@@ -642,12 +584,20 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
                                            : launch_fused_t<TT, MM, false>(S, s);
         NNP_FUSED(4, 0)
         NNP_FUSED(8, 0)
+        NNP_FUSED(10, 0)
+        NNP_FUSED(16, 0)
         NNP_FUSED(4, 1)
         NNP_FUSED(8, 1)
+        NNP_FUSED(10, 1)
+        NNP_FUSED(16, 1)
         NNP_FUSED(4, 2)
         NNP_FUSED(8, 2)
+        NNP_FUSED(10, 2)
+        NNP_FUSED(16, 2)
         NNP_FUSED(4, 3)
         NNP_FUSED(8, 3)
+        NNP_FUSED(10, 3)
+        NNP_FUSED(16, 3)
 #undef NNP_FUSED
         return hipErrorInvalidValue;
     }
@@ -672,17 +622,19 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
 
 hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces)
 {
-    hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + kGatherAtoms - 1) / kGatherAtoms), dim3(64 * kGatherAtoms), 0,
+    hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + kGatherThreads - 1) / kGatherThreads), dim3(kGatherThreads), 0,
                        s, S, dt, mode, forces ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_store_forward(const Sys& S, int mode, int T, hipStream_t s)
+hipError_t launch_store_forward(const Sys& S, int mode, int tile_atoms, hipStream_t s)
 {
     const bool grad = true;
     hipError_t e = launch_descriptors_only(S, s);
     if (e != hipSuccess) return e;
     e = hipErrorInvalidValue;
+    // the network kernel takes tiles of up to T atoms: 8 or 16 columns
+    const int T = tile_atoms <= 8 ? 8 : 16;
     NNP_MLP(8, 0)
     NNP_MLP(16, 0)
     NNP_MLP(8, 1)

@@ -74,7 +74,7 @@ def _params(P, s, **kw):
     ("skin", -1.0, 1),
     ("max_neighbors", 300, 1),
     ("atoms_per_tile", 12, 1),
-    ("atoms_per_tile", 16, 1),
+    ("atoms_per_tile", 6, 1),
 ])
 def test_create_rejects_invalid_params(field, value, status):
     import paper_2412_18271_amd as P

@@ -64,9 +64,11 @@ def test_descriptors_match_oracle(make_system):
 
 
 @pytest.mark.parametrize("path,dtype,T", [("plain", "fp32", 16), ("plain", "fp32", 8), ("fused", "fp32", 8),
-                                          ("fused", "fp32", 4), ("plain", "bf16", 16), ("fused", "bf16", 8),
-                                          ("fused", "bf16", 4), ("plain", "bf16x3", 16), ("fused", "bf16x3", 8),
-                                          ("fused", "bf16x3", 4)])
+                                          ("fused", "fp32", 4), ("fused", "fp32", 10), ("fused", "fp32", 16),
+                                          ("plain", "bf16", 16), ("fused", "bf16", 8), ("fused", "bf16", 4),
+                                          ("fused", "bf16", 10), ("plain", "bf16x3", 16), ("fused", "bf16x3", 8),
+                                          ("fused", "bf16x3", 4), ("fused", "bf16x3", 10), ("fused", "bf16x3", 16),
+                                          ("fused", "bf16x3", 0)])
 @pytest.mark.parametrize("name", ["mol22", "cluster2500"])
 def test_energy_forces_match_oracle(oracle_cache, name, path, dtype, T):
     s, Eo, Eio, Fo = oracle_cache(name)
