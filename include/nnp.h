@@ -101,10 +101,11 @@ typedef struct {
     double skin;                 /* pair-list skin in A (e.g. 1.0), >= 0 */
     int32_t max_neighbors;       /* capacity of one atom's pair list (cutoff 5.2 + skin),
                                     <= 256; 0 selects 192 */
-    int32_t atoms_per_tile;      /* atoms per workgroup: 4, 8, 10 or 16 (fused path), 8 or
-                                    16 (plain path); 0 selects 16 (plain) or, for the fused
-                                    path, 10 when that gives at most one workgroup per
-                                    compute unit and 8 would not, else 8 */
+    int32_t atoms_per_tile;      /* atoms per workgroup: 4, 8, 10 or, with the BF16 and
+                                    split-BF16 networks, 16 (fused path); 8 or 16 (plain
+                                    path); 0 selects 16 (plain) or, for the fused path, 10
+                                    when that gives at most one workgroup per compute unit
+                                    and 8 would not, else 8 */
     void* stream;                /* hipStream_t to run on (see use_stream) */
     int32_t use_stream;          /* nonzero: run on `stream` even when it is NULL (the null
                                     stream, e.g. PyTorch's default stream); zero: a NULL

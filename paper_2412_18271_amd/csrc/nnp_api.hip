@@ -159,7 +159,11 @@ nnp_status check_positions(nnp_context* c, const double* pos)
 // (workgroup b runs on XCD b mod 8), so the table is permuted to give each XCD
 // one contiguous run of tiles: an XCD then meets one or two elements and its
 // L2 holds only their weight fragments.
-bool fused_tile_ok(int T) { return T == 4 || T == 8 || T == 10 || T == 16; }
+// Tiles of 16 atoms exceed the LDS of a CU with the FP32 and FP8 networks.
+bool fused_tile_ok(int T, nnp_dtype d)
+{
+    return T == 4 || T == 8 || T == 10 || (T == 16 && (d == NNP_MLP_BF16 || d == NNP_MLP_BF16_SPLIT));
+}
 
 std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
 {
@@ -569,8 +573,8 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
     if (p->rebuild_every < 1) return msg = "rebuild_every must be >= 1", NNP_ERR_ARG;
     if (!(p->skin >= 0.0) || !std::isfinite(p->skin) || p->skin > 5.0) return msg = "skin must be in [0, 5] A", NNP_ERR_ARG;
     if (p->max_neighbors < 0 || p->max_neighbors > kCapMax) return msg = "max_neighbors must be in [0, 256]", NNP_ERR_ARG;
-    if (p->path == NNP_PATH_FUSED && p->atoms_per_tile != 0 && !fused_tile_ok(p->atoms_per_tile))
-        return msg = "atoms_per_tile of the fused path must be 0, 4, 8, 10 or 16", NNP_ERR_ARG;
+    if (p->path == NNP_PATH_FUSED && p->atoms_per_tile != 0 && !fused_tile_ok(p->atoms_per_tile, p->mlp_dtype))
+        return msg = "atoms_per_tile of the fused path must be 0, 4, 8, 10 or (BF16 networks) 16", NNP_ERR_ARG;
     if (p->path == NNP_PATH_PLAIN && p->atoms_per_tile != 0 && p->atoms_per_tile != 8 && p->atoms_per_tile != 16)
         return msg = "atoms_per_tile of the plain path must be 0, 8 or 16", NNP_ERR_ARG;
     return NNP_OK;
@@ -1120,14 +1124,16 @@ nnp_status nnp_autotune(nnp_context* c, const char* cache_path)
             const size_t p = line.find("\"atoms_per_tile\": ");
             if (p == std::string::npos) continue;
             const int T = std::atoi(line.c_str() + p + 18);
-            if (c->path == NNP_PATH_FUSED ? fused_tile_ok(T) : (T == 8 || T == 16)) return retile(c, T);
+            if (c->path == NNP_PATH_FUSED ? fused_tile_ok(T, c->dtype) : (T == 8 || T == 16)) return retile(c, T);
         }
     }
     std::vector<int> cand;
-    if (c->path == NNP_PATH_FUSED)
-        cand = {4, 8, 10, 16};
-    else
+    if (c->path == NNP_PATH_FUSED) {
+        for (int T : {4, 8, 10, 16})
+            if (fused_tile_ok(T, c->dtype)) cand.push_back(T);
+    } else {
         cand = {8, 16};
+    }
     double best = 1e300;
     int bestT = c->T;
     hipEvent_t e0, e1;

@@ -37,13 +37,12 @@ struct Env {
     float4 geo[kRadMax];            // unit vector to the neighbour, distance
     float2 fcr[kRadMax];            // fc(r; 5.2), dfc/dr
     float2 afc[kAngMax];            // fc(r; 3.5), dfc/dr of angular entries
+    int nid[kRadMax];               // internal index of the neighbour
     unsigned short info[kRadMax];   // element | (slot in the pair list) << 2
     unsigned char ang[kAngMax];     // radial-entry index of neighbours within 3.5 A
-    unsigned char smap[kCapMax];    // pair-list slot -> radial entry, or 255
     int nR, nA, nS;                 // radial entries, angular entries, pair-list length
     int aseg[5];                    // angular entries of element s: [aseg[s], aseg[s+1])
 };
-constexpr unsigned char kNoEntry = 255;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -66,7 +65,7 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
 // relative vector is formed in FP64 from the master positions and rounded to
 // FP32, so the descriptor inputs carry FP32 relative precision at any
 // distance from the origin.
-__device__ __forceinline__ void env_append(Env& E, bool valid, int slot, double dxd, double dyd, double dzd,
+__device__ __forceinline__ void env_append(Env& E, bool valid, int slot, int j, double dxd, double dyd, double dzd,
                                            int elem, int& nR, int& nA, int (&nAs)[4], int& over)
 {
     float r = 0.0f;
@@ -83,9 +82,9 @@ __device__ __forceinline__ void env_append(Env& E, bool valid, int slot, double 
     const unsigned long long mR = __ballot(inR), mA = __ballot(inA);
     const int iR = nR + lanes_below(mR);
     const int iA = nA + lanes_below(mA);
-    if (valid) E.smap[slot] = (inR && iR < kRadMax) ? (unsigned char)iR : kNoEntry;
     if (inR && iR < kRadMax) {
         E.geo[iR] = g;
+        E.nid[iR] = j;
         const float x = r * (1.0f / kCutRad);
         E.fcr[iR] = make_float2(0.5f * cospif(x) + 0.5f, -0.5f * (kPi / kCutRad) * sinpif(x));
         E.info[iR] = (unsigned short)(elem | (slot << 2));
@@ -126,47 +125,11 @@ __device__ __forceinline__ void env_finish(const Sys& S, Env& E, int nR, int nA,
     wave_sync();
 }
 
-// Rebuilds the pair list of atom a (all atoms of its molecule closer than
-// 5.2 + skin, ascending index) and fills its environment from the scan.
-__device__ __forceinline__ void build_list_env(const Sys& S, int a, Env& E)
-{
-    const int lane = lane_id();
-    const double4 pa = S.pos[a];
-    const int m = S.mol[a];
-    int count = 0, nR = 0, nA = 0, over = 0;
-    int nAs[4] = {0, 0, 0, 0};
-    const size_t base = (size_t)a * S.cap;
-    for (int e = 0; e < kNumSpecies; ++e) {
-        const int2 rg = S.mrange[m * kNumSpecies + e];
-        for (int c0 = rg.x; c0 < rg.y; c0 += 64) {
-            const int c = c0 + lane;
-            bool ok = false;
-            double dx = 0, dy = 0, dz = 0;
-            if (c < rg.y && c != a) {
-                const double4 pc = S.pos[c];
-                dx = pc.x - pa.x;
-                dy = pc.y - pa.y;
-                dz = pc.z - pa.z;
-                ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
-            }
-            const unsigned long long mk = __ballot(ok);
-            const int slot = count + lanes_below(mk);
-            const bool keep = ok && slot < S.cap;
-            if (keep) S.nbr[base + slot] = c;
-            env_append(E, keep, slot, dx, dy, dz, e, nR, nA, nAs, over);
-            count += __popcll(mk);
-        }
-    }
-    over |= count > S.cap;
-    const int nS = count < S.cap ? count : S.cap;
-    if (lane == 0) {
-        S.ncnt[a] = nS;
-        S.ref[a] = make_float4((float)pa.x, (float)pa.y, (float)pa.z, 0.f);
-    }
-    env_finish(S, E, nR, nA, nAs, nS, over);
-}
+// Candidate chunks of 64 atoms whose positions are loaded together before any
+// of them is tested (the scan is bound by load latency, not arithmetic).
+constexpr int kScanUnroll = 4;
 
-// Builds only the pair list (plain path).
+// Builds only the pair list.
 __device__ __forceinline__ void build_list(const Sys& S, int a)
 {
     const int lane = lane_id();
@@ -176,18 +139,27 @@ __device__ __forceinline__ void build_list(const Sys& S, int a)
     const size_t base = (size_t)a * S.cap;
     for (int e = 0; e < kNumSpecies; ++e) {
         const int2 rg = S.mrange[m * kNumSpecies + e];
-        for (int c0 = rg.x; c0 < rg.y; c0 += 64) {
-            const int c = c0 + lane;
-            bool ok = false;
-            if (c < rg.y && c != a) {
-                const double4 pc = S.pos[c];
-                const double dx = pc.x - pa.x, dy = pc.y - pa.y, dz = pc.z - pa.z;
-                ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
+        for (int c0 = rg.x; c0 < rg.y; c0 += 64 * kScanUnroll) {
+            double4 pc[kScanUnroll];
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int c = c0 + 64 * u + lane;
+                if (c < rg.y) pc[u] = S.pos[c];
             }
-            const unsigned long long mk = __ballot(ok);
-            const int slot = count + lanes_below(mk);
-            if (ok && slot < S.cap) S.nbr[base + slot] = c;
-            count += __popcll(mk);
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                if (c0 + 64 * u >= rg.y) break;  // wave-uniform
+                const int c = c0 + 64 * u + lane;
+                bool ok = false;
+                if (c < rg.y && c != a) {
+                    const double dx = pc[u].x - pa.x, dy = pc[u].y - pa.y, dz = pc[u].z - pa.z;
+                    ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
+                }
+                const unsigned long long mk = __ballot(ok);
+                const int slot = count + lanes_below(mk);
+                if (ok && slot < S.cap) S.nbr[base + slot] = c;
+                count += __popcll(mk);
+            }
         }
     }
     if (lane == 0) {
@@ -210,17 +182,30 @@ __device__ __forceinline__ void load_env(const Sys& S, int a, Env& E)
         const int s = s0 + lane;
         const bool valid = s < nS;
         double dx = 0, dy = 0, dz = 0;
-        int elem = 0;
+        int elem = 0, j = 0;
         if (valid) {
-            const double4 pj = S.pos[S.nbr[base + s]];
+            j = S.nbr[base + s];
+            const double4 pj = S.pos[j];
             dx = pj.x - pa.x;
             dy = pj.y - pa.y;
             dz = pj.z - pa.z;
             elem = (int)pj.w;
         }
-        env_append(E, valid, s, dx, dy, dz, elem, nR, nA, nAs, over);
+        env_append(E, valid, s, j, dx, dy, dz, elem, nR, nA, nAs, over);
     }
     env_finish(S, E, nR, nA, nAs, nS, over);
+}
+
+// Rebuilds the pair list of atom a (all atoms of its molecule closer than
+// 5.2 + skin, ascending index), then fills its environment from the new list:
+// the cutoff functions are evaluated once per neighbour, not once per
+// scanned chunk.  The fence makes the list written by the wave's lanes
+// visible to all of them.
+__device__ __forceinline__ void build_list_env(const Sys& S, int a, Env& E)
+{
+    build_list(S, a);
+    __threadfence_block();
+    load_env(S, a, E);
 }
 
 // Radial features G[0..63] of the wave's atom.  Lane (k, q): Gaussian k,
@@ -409,14 +394,27 @@ __device__ __forceinline__ void angular_features(const Env& E, float* acc)
 #pragma unroll
     for (int f = 0; f < 32; ++f) t[f] = 0.f;
     if (R.p >= 0) {
-        int ex = E.ang[run_x(R)];
-        float4 gx = E.geo[ex];
+        // the neighbours of the next pair are read from LDS before the terms of
+        // the current one are computed (their latency overlaps the arithmetic)
+        float4 gx = E.geo[E.ang[run_x(R)]];
         float fx = E.afc[run_x(R)].x;
+        float4 gy = E.geo[E.ang[run_y(R)]];
+        float fy = E.afc[run_y(R)].x;
         for (int it = 0; it < R.left; ++it) {
-            const int y = run_y(R);
-            const int ey = E.ang[y];
-            const float4 gy = E.geo[ey];
-            const float fy = E.afc[y].x;
+            const bool more = it + 1 < R.left;
+            const bool xc = run_next(R);
+            float4 gxn = gx, gyn = gy;
+            float fxn = fx, fyn = fy;
+            if (more) {
+                const int y = run_y(R);
+                gyn = E.geo[E.ang[y]];
+                fyn = E.afc[y].x;
+                if (xc) {
+                    const int x = run_x(R);
+                    gxn = E.geo[E.ang[x]];
+                    fxn = E.afc[x].x;
+                }
+            }
             const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
             const float cp = kCosScale * c;
             const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - cp * cp));
@@ -439,12 +437,10 @@ __device__ __forceinline__ void angular_features(const Env& E, float* acc)
 #pragma unroll
                 for (int m = 0; m < kNumShells; ++m) t[8 * m + n] += u * B[m];
             }
-            if (run_next(R) && it + 1 < R.left) {
-                const int x = run_x(R);
-                ex = E.ang[x];
-                gx = E.geo[ex];
-                fx = E.afc[x].x;
-            }
+            gx = gxn;
+            fx = fxn;
+            gy = gyn;
+            fy = fyn;
         }
     }
     const int p = R.p;
@@ -520,15 +516,29 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
         gm[4 * q + 2] = v.z;
         gm[4 * q + 3] = v.w;
     }
-    int ex = E.ang[run_x(R)];
-    float4 gx = E.geo[ex];
-    float2 fx = E.afc[run_x(R)];
+    int ex = E.ang[run_x(R)], ey = E.ang[run_y(R)];
+    float4 gx = E.geo[ex], gy = E.geo[ey];
+    float2 fx = E.afc[run_x(R)], fy = E.afc[run_y(R)];
     float ax = 0.f, ay = 0.f, az = 0.f;  // gradient of E_a with respect to x_x
     for (int it = 0; it < R.left; ++it) {
-        const int y = run_y(R);
-        const int ey = E.ang[y];
-        const float4 gy = E.geo[ey];
-        const float2 fy = E.afc[y];
+        // next pair's neighbours first (see angular_features)
+        const bool more = it + 1 < R.left;
+        const bool xc = run_next(R) && more;
+        int exn = ex, eyn = ey;
+        float4 gxn = gx, gyn = gy;
+        float2 fxn = fx, fyn = fy;
+        if (more) {
+            const int y = run_y(R);
+            eyn = E.ang[y];
+            gyn = E.geo[eyn];
+            fyn = E.afc[y];
+            if (xc) {
+                const int x = run_x(R);
+                exn = E.ang[x];
+                gxn = E.geo[exn];
+                fxn = E.afc[x];
+            }
+        }
         const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
         const float cp = kCosScale * c;
         const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - cp * cp));
@@ -582,16 +592,18 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
         atomicAdd(&facc[3 * ey + 0], -gyx);
         atomicAdd(&facc[3 * ey + 1], -gyy);
         atomicAdd(&facc[3 * ey + 2], -gyz);
-        if (run_next(R) && it + 1 < R.left) {
+        if (xc) {
             atomicAdd(&facc[3 * ex + 0], -ax);
             atomicAdd(&facc[3 * ex + 1], -ay);
             atomicAdd(&facc[3 * ex + 2], -az);
             ax = ay = az = 0.f;
-            const int x = run_x(R);
-            ex = E.ang[x];
-            gx = E.geo[ex];
-            fx = E.afc[x];
         }
+        ex = exn;
+        ey = eyn;
+        gx = gxn;
+        gy = gyn;
+        fx = fxn;
+        fy = fyn;
     }
     atomicAdd(&facc[3 * ex + 0], -ax);
     atomicAdd(&facc[3 * ex + 1], -ay);
@@ -607,7 +619,6 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
 __device__ __forceinline__ void accumulate_forces(const Sys& S, int a, const Env& E, const float* facc)
 {
     const int lane = lane_id();
-    const size_t base = (size_t)a * S.cap;
     long long sx = 0, sy = 0, sz = 0;
     bool bad = false;
     for (int e = lane; e < E.nR; e += 64) {
@@ -616,11 +627,10 @@ __device__ __forceinline__ void accumulate_forces(const Sys& S, int a, const Env
             bad = true;
             continue;
         }
-        const int j = S.nbr[base + (E.info[e] >> 2)];
         const long long qx = __double2ll_rn((double)fx * kFixScale);
         const long long qy = __double2ll_rn((double)fy * kFixScale);
         const long long qz = __double2ll_rn((double)fz * kFixScale);
-        unsigned long long* fj = S.facc + 4 * (size_t)j;
+        unsigned long long* fj = S.facc + 4 * (size_t)E.nid[e];
         atomicAdd(fj + 0, (unsigned long long)qx);
         atomicAdd(fj + 1, (unsigned long long)qy);
         atomicAdd(fj + 2, (unsigned long long)qz);
@@ -819,7 +829,9 @@ __device__ __forceinline__ floatx4 mfma_tile(const bf16x8* __restrict__ fhi, con
     const bool live = col < T;
     const bf16x8 zero = {};
     const int off = (live ? col : 0) * ld + kq;
-#pragma unroll
+    // a partial unroll bounds the fragments in flight (registers) in the
+    // split mode, which reads twice the operands per step
+#pragma unroll(SPLIT ? 4 : 6)
     for (int kt = 0; kt < KT; ++kt) {
         const bf16x8 a = fhi[kt * 64 + lane];
         bf16x8 bh = *reinterpret_cast<const bf16x8*>(bhi + off + kt * 32);

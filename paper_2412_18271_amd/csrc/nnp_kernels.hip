@@ -585,7 +585,6 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(4, 0)
         NNP_FUSED(8, 0)
         NNP_FUSED(10, 0)
-        NNP_FUSED(16, 0)
         NNP_FUSED(4, 1)
         NNP_FUSED(8, 1)
         NNP_FUSED(10, 1)
@@ -597,7 +596,6 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(4, 3)
         NNP_FUSED(8, 3)
         NNP_FUSED(10, 3)
-        NNP_FUSED(16, 3)
 #undef NNP_FUSED
         return hipErrorInvalidValue;
     }
