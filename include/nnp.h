@@ -220,14 +220,15 @@ nnp_status nnp_autotune(nnp_context* ctx, const char* cache_path);
 nnp_status nnp_time_kernels(nnp_context* ctx, int32_t reps, double* ms);
 
 /* Event-timed MD: runs n_steps velocity-Verlet steps like nnp_step without
- * a graph, recording a HIP event on the context stream before every
- * evaluation launch, between it and the force-gather / integration launch,
- * and after the last step.  ms[0] receives the average milliseconds of the
- * evaluation kernel(s) per step, ms[1] that of the gather / integration
- * kernel, ms[2] the average wall time per step between the first and the
- * last event.  The trajectory advances exactly as with nnp_step (pair-list
- * rebuilds included).  Used by the benchmark's roofline report.
- * Synchronises; n_steps >= 1, dt > 0. */
+ * a graph; every kernel dispatch of the evaluation and of the force-sum /
+ * integration kernel carries HIP events that the dispatch itself stamps at
+ * the start and the end of its execution (on the context stream).  ms[0]
+ * receives the average milliseconds per step of the evaluation kernel(s)
+ * (first dispatch start to last dispatch end), ms[1] that of the force-sum /
+ * integration kernel, ms[2] the average time per step from the first
+ * evaluation's start to the last integration's end.  The trajectory
+ * advances exactly as with nnp_step (pair-list rebuilds included).  Used by
+ * the benchmark's roofline report.  Synchronises; n_steps >= 1, dt > 0. */
 nnp_status nnp_time_steps(nnp_context* ctx, double dt_fs, int32_t n_steps, double* ms);
 
 /* E4M3 encodings of x[n]: host_out by the library's host encoder (used for

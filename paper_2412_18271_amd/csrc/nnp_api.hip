@@ -1075,30 +1075,31 @@ nnp_status nnp_time_steps(nnp_context* c, double dt, int32_t nsteps, double* ms)
         HIP_TRY(c, enqueue_compute(c, true));
         c->forces_current = true;
     }
-    // ev[2i] before evaluation i, ev[2i+1] between it and gather i, ev[2n] at the end
-    std::vector<hipEvent_t> ev(2 * (size_t)nsteps + 1, nullptr);
+    // per step: start / end of the evaluation kernel(s) and of the gather /
+    // integration kernel, stamped by the dispatches themselves
+    std::vector<hipEvent_t> ev(4 * (size_t)nsteps, nullptr);
     hipError_t e = hipSuccess;
     for (auto& x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) e = launch_kickdrift(c->S, dt, c->stream);
     for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
-        e = hipEventRecord(ev[2 * i], c->stream);
-        if (e == hipSuccess) e = enqueue_eval(c, true);
-        if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], c->stream);
-        if (e == hipSuccess) e = launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream);
+        e = launch_eval(c->S, c->path == NNP_PATH_FUSED ? 1 : 0, mode_of(c), c->T, true, c->stream, ev[4 * i],
+                        ev[4 * i + 1]);
+        if (e == hipSuccess)
+            e = launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream, true, ev[4 * i + 2],
+                                        ev[4 * i + 3]);
     }
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * nsteps], c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * nsteps]);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4 * (size_t)nsteps - 1]);
     double sum_eval = 0.0, sum_gather = 0.0;
     for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
         float a = 0.f, b = 0.f;
-        e = hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]);
+        e = hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]);
         sum_eval += a;
         sum_gather += b;
     }
     float total = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&total, ev[0], ev[2 * nsteps]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&total, ev[0], ev[4 * (size_t)nsteps - 1]);
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return hip_fail(c, e, "timed steps");

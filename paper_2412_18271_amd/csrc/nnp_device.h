@@ -610,30 +610,96 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
     atomicAdd(&facc[3 * ex + 2], -az);
 }
 
-// Adds the forces of E_a to the fixed-point accumulators: each neighbour
-// within 5.2 A receives its force (LDS facc[3 * entry]), atom a receives
-// minus their sum (translation invariance of E_a).  Components are rounded
-// to multiples of 2^-32 eV/A once per neighbour; the integer sums do not
-// depend on the order in which workgroups add.  A non-finite component or
-// one beyond kFixMax sets the non-finite flag instead of being added.
-__device__ __forceinline__ void accumulate_forces(const Sys& S, int a, const Env& E, const float* facc)
+// Fixed-point force of one neighbour entry (kFixScale units), or false when
+// a component is not finite or beyond kFixMax.
+__device__ __forceinline__ bool fixed_force(const float* facc, int e, long long& qx, long long& qy, long long& qz)
+{
+    const float fx = facc[3 * e], fy = facc[3 * e + 1], fz = facc[3 * e + 2];
+    if (!(fabsf(fx) < kFixMax && fabsf(fy) < kFixMax && fabsf(fz) < kFixMax)) return false;
+    qx = __double2ll_rn((double)fx * kFixScale);
+    qy = __double2ll_rn((double)fy * kFixScale);
+    qz = __double2ll_rn((double)fz * kFixScale);
+    return true;
+}
+
+__device__ __forceinline__ void global_force_add(const Sys& S, int j, long long qx, long long qy, long long qz)
+{
+    unsigned long long* fj = S.facc + 4 * (size_t)j;
+    atomicAdd(fj + 0, (unsigned long long)qx);
+    atomicAdd(fj + 1, (unsigned long long)qy);
+    atomicAdd(fj + 2, (unsigned long long)qz);
+}
+
+// Workgroup table that merges the force contributions of a tile's atoms per
+// receiving atom before they go to HBM (the atoms of a tile are spatial
+// neighbours and share most of their neighbours).  Open addressing over nh
+// slots: key = atom index (-1 empty), three fixed-point sums.
+struct ForceTable {
+    int* key;
+    long long* v;  // [3][nh]
+    int nh;
+};
+
+__device__ __forceinline__ ForceTable force_table(void* mem, size_t bytes)
+{
+    ForceTable t;
+    t.nh = (int)(bytes / (sizeof(int) + 3 * sizeof(long long))) & ~1;
+    t.v = reinterpret_cast<long long*>(mem);
+    t.key = reinterpret_cast<int*>(t.v + 3 * (size_t)t.nh);
+    return t;
+}
+
+__device__ __forceinline__ void table_clear(const ForceTable& t, int tid, int nthr)
+{
+    for (int i = tid; i < t.nh; i += nthr) {
+        t.key[i] = -1;
+        t.v[i] = 0;
+        t.v[t.nh + i] = 0;
+        t.v[2 * t.nh + i] = 0;
+    }
+}
+
+constexpr int kTableProbes = 32;
+
+// Adds (qx, qy, qz) for atom j to the table; past kTableProbes occupied
+// slots it goes straight to HBM.  Integer sums: the result does not depend
+// on the order of the adds.
+__device__ __forceinline__ void table_add(const Sys& S, const ForceTable& t, int j, long long qx, long long qy,
+                                          long long qz)
+{
+    unsigned h = (unsigned)(((unsigned long long)((unsigned)j * 0x9E3779B1u) * (unsigned)t.nh) >> 32);
+    for (int probe = 0; probe < kTableProbes; ++probe) {
+        int k = t.key[h];
+        if (k == -1) k = atomicCAS(&t.key[h], -1, j);
+        if (k == -1 || k == j) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&t.v[h]), (unsigned long long)qx);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&t.v[t.nh + h]), (unsigned long long)qy);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&t.v[2 * t.nh + h]), (unsigned long long)qz);
+            return;
+        }
+        h = h + 1 == (unsigned)t.nh ? 0u : h + 1;
+    }
+    global_force_add(S, j, qx, qy, qz);
+}
+
+// Forces of E_a for the wave's atom a: each neighbour within 5.2 A receives
+// its force (LDS facc[3 * entry]), a receives minus their sum (translation
+// invariance of E_a).  Components are rounded to multiples of 2^-32 eV/A
+// once per neighbour.  A non-finite component or one beyond kFixMax sets
+// the non-finite flag instead of being added.
+__device__ __forceinline__ void table_add_atom(const Sys& S, const ForceTable& t, int a, const Env& E,
+                                               const float* facc)
 {
     const int lane = lane_id();
     long long sx = 0, sy = 0, sz = 0;
     bool bad = false;
     for (int e = lane; e < E.nR; e += 64) {
-        const float fx = facc[3 * e], fy = facc[3 * e + 1], fz = facc[3 * e + 2];
-        if (!(fabsf(fx) < kFixMax && fabsf(fy) < kFixMax && fabsf(fz) < kFixMax)) {
+        long long qx, qy, qz;
+        if (!fixed_force(facc, e, qx, qy, qz)) {
             bad = true;
             continue;
         }
-        const long long qx = __double2ll_rn((double)fx * kFixScale);
-        const long long qy = __double2ll_rn((double)fy * kFixScale);
-        const long long qz = __double2ll_rn((double)fz * kFixScale);
-        unsigned long long* fj = S.facc + 4 * (size_t)E.nid[e];
-        atomicAdd(fj + 0, (unsigned long long)qx);
-        atomicAdd(fj + 1, (unsigned long long)qy);
-        atomicAdd(fj + 2, (unsigned long long)qz);
+        table_add(S, t, E.nid[e], qx, qy, qz);
         sx += qx;
         sy += qy;
         sz += qz;
@@ -644,13 +710,17 @@ __device__ __forceinline__ void accumulate_forces(const Sys& S, int a, const Env
         sy += __shfl_xor(sy, off);
         sz += __shfl_xor(sz, off);
     }
-    if (lane == 0) {
-        unsigned long long* fa = S.facc + 4 * (size_t)a;
-        atomicAdd(fa + 0, (unsigned long long)(-sx));
-        atomicAdd(fa + 1, (unsigned long long)(-sy));
-        atomicAdd(fa + 2, (unsigned long long)(-sz));
-    }
+    if (lane == 0) table_add(S, t, a, -sx, -sy, -sz);
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&S.st->nonfinite, 1);
+}
+
+// Adds the table's sums to the HBM accumulators (workgroup-wide).
+__device__ __forceinline__ void table_flush(const Sys& S, const ForceTable& t, int tid, int nthr)
+{
+    for (int i = tid; i < t.nh; i += nthr) {
+        const int j = t.key[i];
+        if (j >= 0) global_force_add(S, j, t.v[i], t.v[t.nh + i], t.v[2 * t.nh + i]);
+    }
 }
 
 // ------------------------------------------------------------------------

@@ -13,6 +13,8 @@
 // velocity-Verlet update in FP64, per-molecule FP64 energy sums, and the
 // device step-state update by the last workgroup (completion counter).
 #include "nnp_device.h"
+#include <hip/hip_ext.h>
+
 #include "nnp_launch.h"
 
 namespace nnp {
@@ -104,7 +106,14 @@ __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
         __syncthreads();
         if (act) adjoint_angular(E, Grow, fa);
         __syncthreads();
-        if (act) accumulate_forces(S, a, E, fa);
+        // merge the tile's forces per receiving atom in the G rows (dE/dG is
+        // no longer read)
+        const ForceTable ft = force_table(sm.G, sizeof(sm.G));
+        table_clear(ft, tid, 64 * T);
+        __syncthreads();
+        if (act) table_add_atom(S, ft, a, E, fa);
+        __syncthreads();
+        table_flush(S, ft, tid, 64 * T);
     }
 }
 
@@ -186,7 +195,12 @@ __global__ __launch_bounds__(256) void k_adjoint(Sys S)
     __syncthreads();
     if (a < S.n) adjoint_angular(env[wave], gr, fa);
     __syncthreads();
-    if (a < S.n) accumulate_forces(S, a, env[wave], fa);
+    const ForceTable ft = force_table(g, sizeof(g));
+    table_clear(ft, threadIdx.x, 256);
+    __syncthreads();
+    if (a < S.n) table_add_atom(S, ft, a, env[wave], fa);
+    __syncthreads();
+    table_flush(S, ft, threadIdx.x, 256);
 }
 
 // --------------------------------------------------- gather + integrate ---
@@ -547,9 +561,9 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
 // ------------------------------------------------------------ launchers ---
 
 template <int T, int MODE, bool GRAD>
-static hipError_t launch_fused_t(const Sys& S, hipStream_t s)
+static hipError_t launch_fused_t(const Sys& S, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL((k_eval_fused<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, S);
+    hipExtLaunchKernelGGL((k_eval_fused<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, ev0, ev1, 0, S);
     return hipGetLastError();
 }
 
@@ -562,11 +576,11 @@ static hipError_t launch_mlp_t(const Sys& S, hipStream_t s)
 
 hipError_t launch_descriptors_only(const Sys& S, hipStream_t s);
 
-static hipError_t launch_cells(const Sys& S, hipStream_t s)
+static hipError_t launch_cells(const Sys& S, hipStream_t s, hipEvent_t ev0)
 {
     if (S.ncells <= 0) return hipSuccess;
     const int nb = (S.n + 255) / 256;
-    hipLaunchKernelGGL(k_cell_zero, dim3(min((S.ncells + 255) / 256, 1024)), dim3(256), 0, s, S);
+    hipExtLaunchKernelGGL(k_cell_zero, dim3(min((S.ncells + 255) / 256, 1024)), dim3(256), 0, s, ev0, nullptr, 0, S);
     hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, S);
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, S);
     hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, s, S);
@@ -574,14 +588,16 @@ static hipError_t launch_cells(const Sys& S, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s)
+hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1)
 {
-    hipError_t ec = launch_cells(S, s);
+    hipError_t ec = launch_cells(S, s, ev0);
     if (ec != hipSuccess) return ec;
+    if (S.ncells > 0) ev0 = nullptr;  // stamped by the first cell-list kernel
     if (path == 1) {
-#define NNP_FUSED(TT, MM)                                                            \
-    if (T == TT && mode == MM) return grad ? launch_fused_t<TT, MM, true>(S, s)      \
-                                           : launch_fused_t<TT, MM, false>(S, s);
+#define NNP_FUSED(TT, MM)                                                                    \
+    if (T == TT && mode == MM) return grad ? launch_fused_t<TT, MM, true>(S, s, ev0, ev1)    \
+                                           : launch_fused_t<TT, MM, false>(S, s, ev0, ev1);
         NNP_FUSED(4, 0)
         NNP_FUSED(8, 0)
         NNP_FUSED(10, 0)
@@ -600,7 +616,7 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         return hipErrorInvalidValue;
     }
     const int nb4 = (S.n + 3) / 4;
-    hipLaunchKernelGGL(k_lists, dim3(nb4), dim3(256), 0, s, S);
+    hipExtLaunchKernelGGL(k_lists, dim3(nb4), dim3(256), 0, s, ev0, nullptr, 0, S);
     hipLaunchKernelGGL(k_descriptors, dim3(nb4), dim3(256), 0, s, S);
     hipError_t e = hipErrorInvalidValue;
 #define NNP_MLP(TT, MM)                                                                                   \
@@ -614,14 +630,17 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
     NNP_MLP(8, 3)
     NNP_MLP(16, 3)
     if (e != hipSuccess) return e;
-    if (grad) hipLaunchKernelGGL(k_adjoint, dim3(nb4), dim3(256), 0, s, S);
+    if (grad) hipExtLaunchKernelGGL(k_adjoint, dim3(nb4), dim3(256), 0, s, nullptr, ev1, 0, S);
+    else if (ev1) e = hipEventRecord(ev1, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces)
+hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces, hipEvent_t ev0,
+                                   hipEvent_t ev1)
 {
-    hipLaunchKernelGGL(k_gather_integrate, dim3((S.n + kGatherThreads - 1) / kGatherThreads), dim3(kGatherThreads), 0,
-                       s, S, dt, mode, forces ? 1 : 0);
+    hipExtLaunchKernelGGL(k_gather_integrate, dim3((S.n + kGatherThreads - 1) / kGatherThreads),
+                          dim3(kGatherThreads), 0, s, ev0, ev1, 0, S, dt, mode, forces ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -698,7 +717,7 @@ hipError_t launch_invalidate_lists(const Sys& S, hipStream_t s)
 
 hipError_t launch_descriptors_only(const Sys& S, hipStream_t s)
 {
-    hipError_t ec = launch_cells(S, s);
+    hipError_t ec = launch_cells(S, s, nullptr);
     if (ec != hipSuccess) return ec;
     const int nb4 = (S.n + 3) / 4;
     hipLaunchKernelGGL(k_lists, dim3(nb4), dim3(256), 0, s, S);

@@ -9,9 +9,14 @@ namespace nnp {
 // path 0 = plain (one kernel per stage), 1 = fused; mode 0 = FP32 VALU,
 // 1 = BF16 MFMA, 2 = split BF16 MFMA (hi/lo operands, three products),
 // 3 = E4M3 MFMA with per-layer scales.
-hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s);
-// Force gather + velocity Verlet + energies + step-state update (see kernel).
-hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces = true);
+// ev0 / ev1 (optional): events stamped by the first and the last kernel
+// dispatch of the evaluation itself (start / end of execution).
+hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Force sums -> FP64 + velocity Verlet + energies + step-state update (see
+// kernel); ev0 / ev1 as for launch_eval.
+hipError_t launch_gather_integrate(const Sys& S, double dt, int mode, hipStream_t s, bool forces = true,
+                                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Stored-intermediates forward (pair list, descriptors -> S.G, network with
 // dE/dG -> S.dG) and the adjoint from S.dG (plain-path kernels, tile size T).
 hipError_t launch_store_forward(const Sys& S, int mode, int T, hipStream_t s);
