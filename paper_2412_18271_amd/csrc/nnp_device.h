@@ -378,76 +378,69 @@ __device__ __forceinline__ float same_group_shr(int p)
     return (q == p && p >= 0) ? 1.f : 0.f;
 }
 
-// Angular features of the wave's atom, accumulated into acc[10][33] (LDS,
-// zeroed beforehand).  Each lane sums the 32 terms of its run in registers;
-// runs of one element pair occupy consecutive lanes, so a segmented scan
-// inside each row of 16 lanes (DPP shifts 1, 2, 4, 8) leaves every
-// (row, element pair) total in the last lane of its segment, and only those
-// lanes add to LDS.  Element-pair blocks 33 floats apart sit in different
-// banks.  All 64 lanes execute the scan.  The caller copies acc into
-// G[64 + 32 p + f].
-__device__ __forceinline__ void angular_features(const Env& E, float* acc)
+// Adds the 32 angular terms of the pairs of run R (atom environment E) to t.
+// The neighbours of the next pair are read from LDS before the terms of the
+// current one are computed (their latency overlaps the arithmetic).
+__device__ __forceinline__ void run_angular_terms(const Env& E, PairRun R, float (&t)[32])
 {
-    const int lane = lane_id();
-    PairRun R = lane_run(E, lane);
-    float t[32];
-#pragma unroll
-    for (int f = 0; f < 32; ++f) t[f] = 0.f;
-    if (R.p >= 0) {
-        // the neighbours of the next pair are read from LDS before the terms of
-        // the current one are computed (their latency overlaps the arithmetic)
-        float4 gx = E.geo[E.ang[run_x(R)]];
-        float fx = E.afc[run_x(R)].x;
-        float4 gy = E.geo[E.ang[run_y(R)]];
-        float fy = E.afc[run_y(R)].x;
-        for (int it = 0; it < R.left; ++it) {
-            const bool more = it + 1 < R.left;
-            const bool xc = run_next(R);
-            float4 gxn = gx, gyn = gy;
-            float fxn = fx, fyn = fy;
-            if (more) {
-                const int y = run_y(R);
-                gyn = E.geo[E.ang[y]];
-                fyn = E.afc[y].x;
-                if (xc) {
-                    const int x = run_x(R);
-                    gxn = E.geo[E.ang[x]];
-                    fxn = E.afc[x].x;
-                }
+    if (R.p < 0) return;
+    float4 gx = E.geo[E.ang[run_x(R)]];
+    float fx = E.afc[run_x(R)].x;
+    float4 gy = E.geo[E.ang[run_y(R)]];
+    float fy = E.afc[run_y(R)].x;
+    for (int it = 0; it < R.left; ++it) {
+        const bool more = it + 1 < R.left;
+        const bool xc = run_next(R);
+        float4 gxn = gx, gyn = gy;
+        float fxn = fx, fyn = fy;
+        if (more) {
+            const int y = run_y(R);
+            gyn = E.geo[E.ang[y]];
+            fyn = E.afc[y].x;
+            if (xc) {
+                const int x = run_x(R);
+                gxn = E.geo[E.ang[x]];
+                fxn = E.afc[x].x;
             }
-            const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
-            const float cp = kCosScale * c;
-            const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - cp * cp));
-            const float w = kTwoPowM31 * fx * fy;
-            const float rbar = 0.5f * (gx.w + gy.w);
-            float B[kNumShells];
-#pragma unroll
-            for (int m = 0; m < kNumShells; ++m) {
-                const float x = rbar - (0.9f + 0.65f * (float)m);
-                B[m] = w * __expf(-kEtaAng * x * x);
-            }
-#pragma unroll
-            for (int n = 0; n < kNumSectors; ++n) {
-                float u = 1.f + cp * kSecCos[n] + sp * kSecSin[n];
-                u = u * u;  // ^2
-                u = u * u;  // ^4
-                u = u * u;  // ^8
-                u = u * u;  // ^16
-                u = u * u;  // ^32
-#pragma unroll
-                for (int m = 0; m < kNumShells; ++m) t[8 * m + n] += u * B[m];
-            }
-            gx = gxn;
-            fx = fxn;
-            gy = gyn;
-            fy = fyn;
         }
+        const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
+        const float cp = kCosScale * c;
+        const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - cp * cp));
+        const float w = kTwoPowM31 * fx * fy;
+        const float rbar = 0.5f * (gx.w + gy.w);
+        float B[kNumShells];
+#pragma unroll
+        for (int m = 0; m < kNumShells; ++m) {
+            const float x = rbar - (0.9f + 0.65f * (float)m);
+            B[m] = w * __expf(-kEtaAng * x * x);
+        }
+#pragma unroll
+        for (int n = 0; n < kNumSectors; ++n) {
+            float u = 1.f + cp * kSecCos[n] + sp * kSecSin[n];
+            u = u * u;  // ^2
+            u = u * u;  // ^4
+            u = u * u;  // ^8
+            u = u * u;  // ^16
+            u = u * u;  // ^32
+#pragma unroll
+            for (int m = 0; m < kNumShells; ++m) t[8 * m + n] += u * B[m];
+        }
+        gx = gxn;
+        fx = fxn;
+        gy = gyn;
+        fy = fyn;
     }
-    const int p = R.p;
-    const float m1 = same_group_shr<1>(p), m2 = same_group_shr<2>(p);
-    const float m4 = same_group_shr<4>(p), m8 = same_group_shr<8>(p);
-    const int pn = __builtin_amdgcn_update_dpp(-3, p, 0x101, 0xF, 0xF, false);  // lane + 1 of the row
-    const bool emit = p >= 0 && pn != p;
+}
+
+// Segmented inclusive scan of the 32 values of t inside each row of 16
+// lanes (DPP shifts 1, 2, 4, 8) over runs of equal key; returns true in the
+// last lane of each (row, key) segment, which then holds the segment's sums.
+// Lanes with key < 0 take no part.  All 64 lanes must execute it.
+__device__ __forceinline__ bool row_segment_sums(int key, float (&t)[32])
+{
+    const float m1 = same_group_shr<1>(key), m2 = same_group_shr<2>(key);
+    const float m4 = same_group_shr<4>(key), m8 = same_group_shr<8>(key);
+    const int kn = __builtin_amdgcn_update_dpp(-3, key, 0x101, 0xF, 0xF, false);  // lane + 1 of the row
 #pragma unroll
     for (int f = 0; f < 32; ++f) {
         float v = t[f];
@@ -457,8 +450,26 @@ __device__ __forceinline__ void angular_features(const Env& E, float* acc)
         v = fmaf(m8, row_shr<8>(v), v);
         t[f] = v;
     }
-    if (emit) {
-        float* dst = acc + kAccStride * p;
+    return key >= 0 && kn != key;
+}
+
+// Angular features of the wave's atom, accumulated into acc[10][33] (LDS,
+// zeroed beforehand).  Each lane sums the 32 terms of its run in registers;
+// runs of one element pair occupy consecutive lanes, so a segmented scan
+// inside each row of 16 lanes leaves every (row, element pair) total in the
+// last lane of its segment, and only those lanes add to LDS (one
+// instruction per feature: a fixed order).  Element-pair blocks 33 floats
+// apart sit in different banks.  The caller copies acc into G[64 + 32 p + f].
+__device__ __forceinline__ void angular_features(const Env& E, float* acc)
+{
+    const int lane = lane_id();
+    const PairRun R = lane_run(E, lane);
+    float t[32];
+#pragma unroll
+    for (int f = 0; f < 32; ++f) t[f] = 0.f;
+    run_angular_terms(E, R, t);
+    if (row_segment_sums(R.p, t)) {
+        float* dst = acc + kAccStride * R.p;
 #pragma unroll
         for (int f = 0; f < 32; ++f) atomicAdd(dst + f, t[f]);
     }
@@ -497,46 +508,37 @@ __device__ __forceinline__ void adjoint_radial(const Env& E, const float* g, flo
     }
 }
 
-// Angular part of the adjoint.  A lane's run belongs to one element-pair
-// block, so its 32 values of dE/dG are read once; the force on the slowly
-// changing neighbour x is summed in registers and added when x changes, the
-// force on y with LDS atomics at every pair.
-__device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, float* facc)
+// Adjoint of the angular terms of run R: with gm the 32 values of dE/dG of
+// the run's element-pair block, add(radial entry, angular entry, v) receives
+// the gradient v of E_a with respect to the position of that neighbour (the
+// force is -v).  The slowly changing neighbour x is summed in registers and
+// handed over when x changes; y at every pair.
+template <class Add>
+__device__ __forceinline__ void adjoint_run(const Env& E, PairRun R, const float (&gm)[32], Add add)
 {
-    const int lane = lane_id();
-    PairRun R = lane_run(E, lane);
     if (R.p < 0) return;
-    float gm[32];
-    const float4* gb = reinterpret_cast<const float4*>(g + 64 + 32 * R.p);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float4 v = gb[q];
-        gm[4 * q + 0] = v.x;
-        gm[4 * q + 1] = v.y;
-        gm[4 * q + 2] = v.z;
-        gm[4 * q + 3] = v.w;
-    }
-    int ex = E.ang[run_x(R)], ey = E.ang[run_y(R)];
+    int xa = run_x(R), ya = run_y(R);
+    int ex = E.ang[xa], ey = E.ang[ya];
     float4 gx = E.geo[ex], gy = E.geo[ey];
-    float2 fx = E.afc[run_x(R)], fy = E.afc[run_y(R)];
-    float ax = 0.f, ay = 0.f, az = 0.f;  // gradient of E_a with respect to x_x
+    float2 fx = E.afc[xa], fy = E.afc[ya];
+    float ax = 0.f, ay = 0.f, az = 0.f;
     for (int it = 0; it < R.left; ++it) {
-        // next pair's neighbours first (see angular_features)
+        // next pair's neighbours first (see run_angular_terms)
         const bool more = it + 1 < R.left;
         const bool xc = run_next(R) && more;
-        int exn = ex, eyn = ey;
+        int xan = xa, yan = ya, exn = ex, eyn = ey;
         float4 gxn = gx, gyn = gy;
         float2 fxn = fx, fyn = fy;
         if (more) {
-            const int y = run_y(R);
-            eyn = E.ang[y];
+            yan = run_y(R);
+            eyn = E.ang[yan];
             gyn = E.geo[eyn];
-            fyn = E.afc[y];
+            fyn = E.afc[yan];
             if (xc) {
-                const int x = run_x(R);
-                exn = E.ang[x];
+                xan = run_x(R);
+                exn = E.ang[xan];
                 gxn = E.geo[exn];
-                fxn = E.afc[x];
+                fxn = E.afc[xan];
             }
         }
         const float c = gx.x * gy.x + gx.y * gy.y + gx.z * gy.z;
@@ -582,22 +584,17 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
         const float dEdrx = pre * (Et * fx.y * fy.x + 0.5f * ff * dEdrb);
         const float dEdry = pre * (Et * fx.x * fy.y + 0.5f * ff * dEdrb);
         const float ix = __builtin_amdgcn_rcpf(gx.w), iy = __builtin_amdgcn_rcpf(gy.w);
-        // gradient of E_a with respect to x_x and x_y; the force is its negative
         ax += dEdrx * gx.x + dEdc * (gy.x - c * gx.x) * ix;
         ay += dEdrx * gx.y + dEdc * (gy.y - c * gx.y) * ix;
         az += dEdrx * gx.z + dEdc * (gy.z - c * gx.z) * ix;
-        const float gyx = dEdry * gy.x + dEdc * (gx.x - c * gy.x) * iy;
-        const float gyy = dEdry * gy.y + dEdc * (gx.y - c * gy.y) * iy;
-        const float gyz = dEdry * gy.z + dEdc * (gx.z - c * gy.z) * iy;
-        atomicAdd(&facc[3 * ey + 0], -gyx);
-        atomicAdd(&facc[3 * ey + 1], -gyy);
-        atomicAdd(&facc[3 * ey + 2], -gyz);
+        add(ey, ya, dEdry * gy.x + dEdc * (gx.x - c * gy.x) * iy, dEdry * gy.y + dEdc * (gx.y - c * gy.y) * iy,
+            dEdry * gy.z + dEdc * (gx.z - c * gy.z) * iy);
         if (xc) {
-            atomicAdd(&facc[3 * ex + 0], -ax);
-            atomicAdd(&facc[3 * ex + 1], -ay);
-            atomicAdd(&facc[3 * ex + 2], -az);
+            add(ex, xa, ax, ay, az);
             ax = ay = az = 0.f;
         }
+        xa = xan;
+        ya = yan;
         ex = exn;
         ey = eyn;
         gx = gxn;
@@ -605,9 +602,37 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
         fx = fxn;
         fy = fyn;
     }
-    atomicAdd(&facc[3 * ex + 0], -ax);
-    atomicAdd(&facc[3 * ex + 1], -ay);
-    atomicAdd(&facc[3 * ex + 2], -az);
+    add(ex, xa, ax, ay, az);
+}
+
+// dE/dG values of element-pair block p of a G row, held in registers.
+__device__ __forceinline__ void load_block(const float* g, int p, float (&gm)[32])
+{
+    const float4* gb = reinterpret_cast<const float4*>(g + 64 + 32 * p);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float4 v = gb[q];
+        gm[4 * q + 0] = v.x;
+        gm[4 * q + 1] = v.y;
+        gm[4 * q + 2] = v.z;
+        gm[4 * q + 3] = v.w;
+    }
+}
+
+// Angular part of the adjoint for the wave's atom: forces added to facc
+// with LDS atomics (one wave per atom, so each address sees the adds of one
+// wave only).
+__device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, float* facc)
+{
+    const PairRun R = lane_run(E, lane_id());
+    if (R.p < 0) return;
+    float gm[32];
+    load_block(g, R.p, gm);
+    adjoint_run(E, R, gm, [&](int e, int, float vx, float vy, float vz) {
+        atomicAdd(&facc[3 * e + 0], -vx);
+        atomicAdd(&facc[3 * e + 1], -vy);
+        atomicAdd(&facc[3 * e + 2], -vz);
+    });
 }
 
 // Fixed-point force of one neighbour entry (kFixScale units), or false when
@@ -723,10 +748,6 @@ __device__ __forceinline__ void table_flush(const Sys& S, const ForceTable& t, i
     }
 }
 
-// ------------------------------------------------------------------------
-// Network on a tile of up to T atoms of one element (workgroup-wide).
-// ------------------------------------------------------------------------
-
 // LDS row strides (elements) of the activation buffers.
 constexpr int kLdG = kNumFeat + 8;  // G / dE/dG rows: fp32, or bf16 hi + lo overlaid
 constexpr int kLd1 = kH1 + 8;       // bf16 rows
@@ -735,6 +756,221 @@ constexpr int kLd3 = kH3 + 8;
 constexpr int kLdF1 = kH1 + 4;      // fp32 rows
 constexpr int kLdF2 = kH2 + 4;
 constexpr int kLdF3 = kH3 + 4;
+
+// ------------------------------------------------------------------------
+// Angular work pooled over the workgroup.  The pairs of all atoms of a tile
+// are dealt out to all its lanes in runs of one (atom, element pair) group,
+// so the angular phases last as long as the tile's mean work instead of its
+// heaviest atom's.  Sums that receive adds from several waves are kept in
+// 64-bit fixed point (2^-32 units): integer addition does not depend on the
+// order of the adds.
+// ------------------------------------------------------------------------
+template <int T>
+struct PoolPlan {
+    int cnt[T * 10];        // pairs of group g = 10 w + p (atom w, element pair p)
+    int first[T * 10 + 1];  // first lane of each group's runs; first[10 T] = lanes used
+    int C;                  // pairs per run
+};
+
+// Group sizes, run length and lane ranges for the first nact atoms of the
+// tile (workgroup-wide; ends with a barrier).  C = ceil(W / 54 T) for W pairs in all keeps the runs within the
+// 64 T lanes: sum_g ceil(cnt_g / C) < W / C + 10 T <= 64 T.
+template <int T>
+__device__ __forceinline__ void pool_plan(const Env* env, int nact, PoolPlan<T>& pl, int tid)
+{
+    constexpr int NG = T * 10, FREE = 64 * T - NG;
+    static_assert(NG <= 128, "two groups per lane of the planning wave");
+    if (tid < NG && tid / 10 >= nact) pl.cnt[tid] = 0;  // no atom in this column of the tile
+    if (tid < NG && tid / 10 < nact) {
+        const Env& E = env[tid / 10];
+        const int p = tid % 10;
+        const int s1 = kPairS1[p], s2 = kPairS2[p];
+        const int n1 = E.aseg[s1 + 1] - E.aseg[s1], n2 = E.aseg[s2 + 1] - E.aseg[s2];
+        pl.cnt[tid] = s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int g0 = 2 * tid, g1 = 2 * tid + 1;
+        const int c0 = g0 < NG ? pl.cnt[g0] : 0, c1 = g1 < NG ? pl.cnt[g1] : 0;
+        int w = c0 + c1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+        const int C = w > FREE ? (w + FREE - 1) / FREE : 1;
+        const int r0 = (c0 + C - 1) / C, r1 = (c1 + C - 1) / C;
+        int incl = r0 + r1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (tid >= off) incl += v;
+        }
+        const int excl = incl - r0 - r1;
+        if (g0 < NG) pl.first[g0] = excl;
+        if (g1 < NG) pl.first[g1] = excl + r0;
+        if (tid == 63) pl.first[NG] = incl;
+        if (tid == 0) pl.C = C;
+    }
+    __syncthreads();
+}
+
+// The run of workgroup lane L (R.p < 0 when L has none); w = its atom.
+template <int T>
+__device__ __forceinline__ PairRun pool_run(const Env* env, const PoolPlan<T>& pl, int L, int& w)
+{
+    constexpr int NG = T * 10;
+    PairRun R;
+    R.p = -1;
+    R.left = 0;
+    w = 0;
+    if (L >= pl.first[NG]) return R;
+    // last group whose first lane is <= L (groups without runs share their
+    // successor's first lane)
+    int lo = 0, hi = NG - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pl.first[mid] <= L)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int g = lo;
+    w = g / 10;
+    const int p = g - 10 * w;
+    const Env& E = env[w];
+    const int q0 = (L - pl.first[g]) * pl.C;
+    const int s1 = kPairS1[p], s2 = kPairS2[p];
+    R.p = p;
+    R.left = min(pl.C, pl.cnt[g] - q0);
+    R.lo1 = E.aseg[s1];
+    R.lo2 = E.aseg[s2];
+    R.n2 = E.aseg[s2 + 1] - E.aseg[s2];
+    R.same = s1 == s2;
+    if (R.same) {
+        pair_of(q0, R.jj, R.kk);
+    } else {
+        int jj = (int)((float)q0 / (float)R.n2);
+        while (jj * R.n2 > q0) --jj;
+        while ((jj + 1) * R.n2 <= q0) ++jj;
+        R.jj = jj;
+        R.kk = q0 - jj * R.n2;
+    }
+    return R;
+}
+
+// x >= 0 (a sum of non-negative terms) in 2^-32 units.
+__device__ __forceinline__ unsigned long long to_fix_pos(float x)
+{
+    const float fl = floorf(x);
+    const unsigned hi = (unsigned)fl;
+    const unsigned lo = (unsigned)((x - fl) * 4294967296.0f);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// |x| < kFixMax in 2^-32 units (two's complement).
+__device__ __forceinline__ long long to_fix(float x)
+{
+    const float fl = floorf(x);
+    const int hi = (int)fl;
+    const unsigned lo = (unsigned)((x - fl) * 4294967296.0f);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | lo);
+}
+
+// Angular features of the tile's atoms: accI[w][32 p + f] (fixed point,
+// zeroed beforehand) receives the row-segment sums (key = group).
+template <int T>
+__device__ __forceinline__ void angular_features_pooled(const Env* env, const PoolPlan<T>& pl,
+                                                        unsigned long long* accI, int tid)
+{
+    int w;
+    const PairRun R = pool_run<T>(env, pl, tid, w);
+    float t[32];
+#pragma unroll
+    for (int f = 0; f < 32; ++f) t[f] = 0.f;
+    run_angular_terms(env[w], R, t);
+    if (row_segment_sums(R.p >= 0 ? 10 * w + R.p : -1, t)) {
+        unsigned long long* dst = accI + 320 * w + 32 * R.p;
+#pragma unroll
+        for (int f = 0; f < 32; ++f) atomicAdd(dst + f, to_fix_pos(t[f]));
+    }
+}
+
+// G[w][64 + i] <- accI[w][i] (workgroup-wide).
+template <int T>
+__device__ __forceinline__ void angular_store_pooled(const unsigned long long* accI, float* G, int tid, int nthr)
+{
+    for (int i = tid; i < T * 320; i += nthr) {
+        const int w = i / 320, f = i - 320 * w;
+        G[w * kLdG + 64 + f] = (float)((double)accI[i] * (1.0 / 4294967296.0));
+    }
+}
+
+// Angular part of the adjoint for the tile: faccA[(w kAngMax + j) 3 + c]
+// (fixed point, zeroed beforehand) receives the force on angular entry j of
+// atom w.  G holds the dE/dG rows.  bad: a component reached kFixMax.
+template <int T>
+__device__ __forceinline__ void adjoint_angular_pooled(const Sys& S, const Env* env, const PoolPlan<T>& pl,
+                                                       const float* G, unsigned long long* faccA, int tid)
+{
+    int w;
+    const PairRun R = pool_run<T>(env, pl, tid, w);
+    bool bad = false;
+    if (R.p >= 0) {
+        float gm[32];
+        load_block(G + w * kLdG, R.p, gm);
+        unsigned long long* fa = faccA + (size_t)w * kAngMax * 3;
+        adjoint_run(env[w], R, gm, [&](int, int j, float vx, float vy, float vz) {
+            if (!(fabsf(vx) < kFixMax && fabsf(vy) < kFixMax && fabsf(vz) < kFixMax)) {
+                bad = true;
+                return;
+            }
+            atomicAdd(fa + 3 * j + 0, (unsigned long long)to_fix(-vx));
+            atomicAdd(fa + 3 * j + 1, (unsigned long long)to_fix(-vy));
+            atomicAdd(fa + 3 * j + 2, (unsigned long long)to_fix(-vz));
+        });
+    }
+    if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&S.st->nonfinite, 1);
+}
+
+// Forces of E_a for the wave's atom a from its radial part (facc, float) and
+// its pooled angular part (faccA, fixed point), merged in the table.
+__device__ __forceinline__ void table_add_atom_pooled(const Sys& S, const ForceTable& t, int a, const Env& E,
+                                                      const float* facc, const unsigned long long* faccA)
+{
+    const int lane = lane_id();
+    long long sx = 0, sy = 0, sz = 0;
+    bool bad = false;
+    for (int e = lane; e < E.nR; e += 64) {
+        long long qx, qy, qz;
+        if (!fixed_force(facc, e, qx, qy, qz)) {
+            bad = true;
+            continue;
+        }
+        table_add(S, t, E.nid[e], qx, qy, qz);
+        sx += qx;
+        sy += qy;
+        sz += qz;
+    }
+    for (int j = lane; j < E.nA; j += 64) {
+        const long long qx = (long long)faccA[3 * j], qy = (long long)faccA[3 * j + 1];
+        const long long qz = (long long)faccA[3 * j + 2];
+        table_add(S, t, E.nid[E.ang[j]], qx, qy, qz);
+        sx += qx;
+        sy += qy;
+        sz += qz;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off);
+        sy += __shfl_xor(sy, off);
+        sz += __shfl_xor(sz, off);
+    }
+    if (lane == 0) table_add(S, t, a, -sx, -sy, -sz);
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&S.st->nonfinite, 1);
+}
+
+// ------------------------------------------------------------------------
+// Network on a tile of up to T atoms of one element (workgroup-wide).
+// ------------------------------------------------------------------------
+
 
 // out[t][o] = sum_k in[t][k] * Wm[k][o] (+ epilogue) for o < M, t < T.
 // Thread = (output o, group of 4 atoms).

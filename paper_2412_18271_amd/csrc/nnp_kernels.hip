@@ -60,7 +60,7 @@ template <int T, int MODE>
 struct FusedSmem {
     Env env[T];
     float G[T * kLdG];
-    union {
+    union __attribute__((aligned(16))) {
         typename MlpSmemOf<T, MODE>::type m;
         float facc[T * 3 * kRadMax];
         float acc[T * 10 * kAccStride];  // angular accumulators (descriptor phase)
@@ -150,6 +150,72 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
     __syncthreads();
     if (a < S.n)
         for (int i = lane; i < kNumFeat; i += 64) S.G[(size_t)a * kNumFeat + i] = Grow[i];
+}
+
+// Fused evaluation with the angular work of the tile pooled over all lanes of
+// the workgroup (see PoolPlan): same stages and outputs as k_eval_fused.
+template <int T, int MODE>
+struct PooledSmem {
+    Env env[T];
+    float G[T * kLdG];
+    PoolPlan<T> plan;
+    union __attribute__((aligned(16))) {  // 16-byte LDS vector accesses
+        typename MlpSmemOf<T, MODE>::type m;
+        unsigned long long accI[T * 320];  // angular features (descriptor phase)
+        struct {
+            float facc[T * 3 * kRadMax];                 // radial part of the forces
+            unsigned long long faccA[T * kAngMax * 3];   // angular part (fixed point)
+        } adj;
+    } u;
+    float E[16];
+};
+
+template <int T, int MODE, bool GRAD>
+__global__ __launch_bounds__(64 * T) void k_eval_pooled(Sys S)
+{
+    __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int4 tile = S.tiles[blockIdx.x];
+    const int a = tile.x + wave;
+    const bool act = wave < tile.y;
+    const bool rb = rebuild_due(S.st, S.rebuild_every);
+    Env& E = sm.env[wave];
+    float* Grow = sm.G + wave * kLdG;
+
+    if (act) {
+        if (rb && S.molgrid[S.mol[a]] < 0)
+            build_list_env(S, a, E);
+        else
+            load_env(S, a, E);
+    }
+    for (int i = tid; i < T * kLdG; i += 64 * T) sm.G[i] = 0.f;
+    for (int i = tid; i < T * 320; i += 64 * T) sm.u.accI[i] = 0ull;
+    __syncthreads();
+    pool_plan<T>(sm.env, tile.y, sm.plan, tid);
+    if (act) radial_features(E, Grow);
+    angular_features_pooled<T>(sm.env, sm.plan, sm.u.accI, tid);
+    __syncthreads();
+    angular_store_pooled<T>(sm.u.accI, sm.G, tid, 64 * T);
+    __syncthreads();
+    run_mlp<T, MODE, GRAD>(S, tile.z, sm.G, sm.u.m, sm.E, tid);
+    __syncthreads();
+    if (act && lane == 0) S.Ei[a] = sm.E[wave];
+    if (GRAD) {
+        for (int i = tid; i < T * kAngMax * 3; i += 64 * T) sm.u.adj.faccA[i] = 0ull;
+        float* fa = sm.u.adj.facc + wave * 3 * kRadMax;
+        if (act) adjoint_radial(E, Grow, fa);
+        __syncthreads();
+        adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.u.adj.faccA, tid);
+        __syncthreads();
+        // merge the tile's forces per receiving atom in the G rows (dE/dG is
+        // no longer read)
+        const ForceTable ft = force_table(sm.G, sizeof(sm.G));
+        table_clear(ft, tid, 64 * T);
+        __syncthreads();
+        if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.u.adj.faccA + (size_t)wave * kAngMax * 3);
+        __syncthreads();
+        table_flush(S, ft, tid, 64 * T);
+    }
 }
 
 // Network of one tile of atoms: G from HBM, dE/dG (when GRAD) and E_i to HBM.
@@ -560,10 +626,18 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
 
 // ------------------------------------------------------------ launchers ---
 
+// Tiles of 10 atoms (one workgroup per CU at 2,500 atoms) pool the angular
+// work; the other tile sizes keep one wave per atom throughout.
+template <int T>
+constexpr bool kPooledTile = T == 10;
+
 template <int T, int MODE, bool GRAD>
 static hipError_t launch_fused_t(const Sys& S, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipExtLaunchKernelGGL((k_eval_fused<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, ev0, ev1, 0, S);
+    if constexpr (kPooledTile<T>)
+        hipExtLaunchKernelGGL((k_eval_pooled<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, ev0, ev1, 0, S);
+    else
+        hipExtLaunchKernelGGL((k_eval_fused<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, ev0, ev1, 0, S);
     return hipGetLastError();
 }
 
