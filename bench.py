@@ -50,7 +50,7 @@ DT_FS = 0.5
 F_TOL = 1e-2
 N_SNAPSHOTS = 10
 VARIANTS = (("fp32", "plain"), ("fp32", "fused"), ("bf16", "fused"), ("bf16x3", "fused"), ("fp8", "fused"))
-KERNEL_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp8": 3}  # template MODE of k_eval_fused
+KERNEL_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp8": 3}  # template MODE of the evaluation kernels
 
 # Algorithmic FLOPs (see the design notes): per radial pair (r < 5.2 A) and
 # per angular triple (both neighbours within 3.5 A), forward descriptor plus
@@ -64,7 +64,7 @@ MI355X_BF16_MFMA_TFLOPS = 2500.0
 MI355X_FP8_MFMA_TFLOPS = 5000.0
 MI355X_HBM_GBS = 8000.0
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_fused_cluster2500_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_pooled_bf16x3_cluster2500_traffic.md")
 KERNEL_SOURCES = ("nnp_kernels.hip", "nnp_device.h", "nnp_internal.h")
 
 
@@ -230,7 +230,6 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     """Markdown summary of a FETCH_SIZE run and a WRITE_SIZE run: per-dispatch
     KiB of the evaluation kernel, scaled by the calibration kernel's reading."""
     dtype, path = variant.split(":")
-    pat = "k_eval_fused<%s, %d," if path == "fused" else "k_mlp<%s, %d,"
 
     def per_kernel(db, counter):
         c = sqlite3.connect(db)
@@ -243,9 +242,9 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
         rows = per_kernel(db, counter)
         cal = [v for k, v in rows if "neg" in k and v > 0.25 * known_kib]
-        ker = [(k, v) for k, v in rows if "k_eval_fused" in k or "k_mlp" in k]
+        ker = [(k, v) for k, v in rows if "k_eval_" in k]
         names = sorted({k for k, _ in ker})
-        mine = [v for k, v in ker if re.search(r"k_eval_fused<\d+, %d," % KERNEL_MODE[dtype], k)]
+        mine = [v for k, v in ker if re.search(r"k_eval_(fused|pooled)<\d+, %d," % KERNEL_MODE[dtype], k)]
         res[counter] = {"cal_kib": float(np.median(cal)) if cal else None,
                         "kernel_kib": float(np.mean(mine)) if mine else None,
                         "dispatches": len(mine), "names": names}
@@ -256,7 +255,7 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     fetch_b = fr["kernel_kib"] * f_factor * 1024
     write_b = wr["kernel_kib"] * w_factor * 1024
     lines = [
-        "# k_eval_fused HBM traffic, cluster2500 (2,500 atoms), %s network" % dtype,
+        "# Evaluation kernel HBM traffic, cluster2500 (2,500 atoms), %s network" % dtype,
         "",
         "Commands (run from the repository root, TMPDIR=/tmp):",
         "",
@@ -269,7 +268,7 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
         "",
         "Calibration kernel: torch.neg over %d MiB of float32 (reads %d MiB, writes %d MiB)." % (mib, mib, mib),
         "",
-        "| counter | calibration reading (KiB) | known (KiB) | scale | k_eval_fused per dispatch (KiB) | dispatches | scaled bytes per launch |",
+        "| counter | calibration reading (KiB) | known (KiB) | scale | evaluation kernel per dispatch (KiB) | dispatches | scaled bytes per launch |",
         "|---|---|---|---|---|---|---|",
         "| FETCH_SIZE | %.1f | %.0f | %.4f | %.1f | %d | %.0f |" % (fr["cal_kib"], known_kib, f_factor,
                                                                   fr["kernel_kib"], fr["dispatches"], fetch_b),
@@ -472,7 +471,8 @@ def main():
     roofline = {
         "bound": "alu", "achieved": valu_tflops, "peak": MI355X_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s", "frac": valu_tflops / MI355X_FP32_VECTOR_TFLOPS, "traffic": traffic,
-        "kernel": "k_eval_fused (%s network): descriptors + network + adjoint" % best["dtype"],
+        "kernel": "evaluation kernel (%s path, %s network): pair list, descriptors, network, adjoint" % (
+            best["path"], best["dtype"]),
         "kernel_ms": best["kernel_ms_eval"],
         "flop_per_launch_valu": valu_flop, "flop_per_launch_mlp": mlp_flop,
         "radial_pairs_per_launch": rad, "angular_triples_per_launch": tri,
