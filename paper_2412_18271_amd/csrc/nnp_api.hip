@@ -47,6 +47,9 @@ struct nnp_context {
     // configuration
     int n = 0, nmol = 0, cap = 160, T = 16;
     bool T_auto = false;  // atoms per tile chosen at layout
+    // tiles on the host: table and the atom of every column (kTileCap per tile)
+    std::vector<int4> tiles;
+    std::vector<int> tile_atoms;
     nnp_dtype dtype = NNP_MLP_FP32;
     nnp_path path = NNP_PATH_FUSED;
     int rebuild_every = 20;
@@ -185,6 +188,73 @@ std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
     return out;
 }
 
+// Tile table and column atoms (the initial tiling: consecutive atoms) to the
+// device.  Synchronous.
+nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
+{
+    c->tiles = tiles;
+    c->tile_atoms.assign(tiles.size() * kTileCap, 0);
+    for (size_t b = 0; b < tiles.size(); ++b)
+        for (int i = 0; i < tiles[b].y; ++i) c->tile_atoms[b * kTileCap + i] = tiles[b].x + i;
+    c->S.ntiles = (int)tiles.size();
+    HIP_TRY(c, hipMemcpy((void*)c->S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((void*)c->S.tile_atoms, c->tile_atoms.data(), sizeof(int) * c->tile_atoms.size(),
+                         hipMemcpyHostToDevice));
+    return NNP_OK;
+}
+
+// Tiles whose atoms pool their angular work (10 per tile) take as long as
+// their total work.  Between blocks of steps the atoms of each element are
+// moved between its tiles, heaviest atom of the heaviest tile for the
+// lightest atom of the lightest tile, while that lowers the heavier of the
+// two; the work per atom comes from the last evaluation.  Deterministic (a
+// function of the recorded work).  Synchronises the context stream.
+bool balanced_tiles(const nnp_context* c) { return c->path == NNP_PATH_FUSED && c->T == 10; }
+
+nnp_status rebalance_tiles(nnp_context* c)
+{
+    if (!balanced_tiles(c) || !c->laid_out) return NNP_OK;
+    const int n = c->n, nt = (int)c->tiles.size();
+    std::vector<int> work(n);
+    HIP_TRY(c, hipMemcpyAsync(work.data(), c->S.work, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    bool changed = false;
+    for (int e = 0; e < kNumSpecies; ++e) {
+        std::vector<int> tl;
+        for (int b = 0; b < nt; ++b)
+            if (c->tiles[b].z == e) tl.push_back(b);
+        if (tl.size() < 2) continue;
+        std::vector<long long> W(nt, 0);
+        for (int b : tl)
+            for (int i = 0; i < c->tiles[b].y; ++i) W[b] += work[c->tile_atoms[b * kTileCap + i]];
+        for (size_t it = 0; it < 8 * tl.size(); ++it) {
+            int h = tl[0], l = tl[0];
+            for (int b : tl) {
+                if (W[b] > W[h]) h = b;
+                if (W[b] < W[l]) l = b;
+            }
+            if (h == l) break;
+            int ih = 0, il = 0;
+            for (int i = 1; i < c->tiles[h].y; ++i)
+                if (work[c->tile_atoms[h * kTileCap + i]] > work[c->tile_atoms[h * kTileCap + ih]]) ih = i;
+            for (int i = 1; i < c->tiles[l].y; ++i)
+                if (work[c->tile_atoms[l * kTileCap + i]] < work[c->tile_atoms[l * kTileCap + il]]) il = i;
+            const int ah = c->tile_atoms[h * kTileCap + ih], al = c->tile_atoms[l * kTileCap + il];
+            const long long d = (long long)work[ah] - work[al];
+            if (d <= 0 || std::max(W[h] - d, W[l] + d) >= W[h]) break;
+            std::swap(c->tile_atoms[h * kTileCap + ih], c->tile_atoms[l * kTileCap + il]);
+            W[h] -= d;
+            W[l] += d;
+            changed = true;
+        }
+    }
+    if (changed)
+        HIP_TRY(c, hipMemcpyAsync((void*)c->S.tile_atoms, c->tile_atoms.data(), sizeof(int) * c->tile_atoms.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NNP_OK;
+}
+
 // Builds the internal order from the first positions and uploads every
 // per-atom constant.
 nnp_status lay_out(nnp_context* c, const double* pos)
@@ -311,7 +381,10 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     HIP_TRY(c, hipMemcpy((void*)S.mass, mass.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy((void*)S.mol, mol.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy((void*)S.mrange, mr.data(), sizeof(int2) * mr.size(), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy((void*)S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    {
+        const nnp_status ts = upload_tiles(c, tiles);
+        if (ts != NNP_OK) return ts;
+    }
     HIP_TRY(c, hipMemcpy((void*)S.perm, perm_dev.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     // the context stream does not synchronise with the null stream
     HIP_TRY(c, hipDeviceSynchronize());
@@ -327,9 +400,9 @@ nnp_status retile(nnp_context* c, int T)
     std::vector<int> elem(c->n);
     for (int k = 0; k < c->n; ++k) elem[k] = c->species[c->perm[k]];
     const std::vector<int4> tiles = make_tiles(elem, T);
-    c->S.ntiles = (int)tiles.size();
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipMemcpy((void*)c->S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    const nnp_status ts = upload_tiles(c, tiles);
+    if (ts != NNP_OK) return ts;
     HIP_TRY(c, hipDeviceSynchronize());
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
     c->graphs.clear();
@@ -645,6 +718,8 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(mol, const int*, n)
     ALLOC(mrange, const int2*, nm * 4)
     ALLOC(tiles, const int4*, n)
+    ALLOC(tile_atoms, const int*, (size_t)n * kTileCap)
+    ALLOC(work, int*, n)
     ALLOC(nbr, int*, n * cap)
     ALLOC(ncnt, int*, n)
     ALLOC(facc, unsigned long long*, 4 * (size_t)n)
@@ -768,6 +843,13 @@ nnp_status nnp_set_state(nnp_context* c, const double* pos, const double* vel)
         if (e != hipSuccess) return hip_fail(c, e, "invalidate");
         c->forces_current = false;
         c->kick_pending = false;
+        // a new trajectory starts from the initial tiling with no recorded work
+        if (balanced_tiles(c)) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            const nnp_status ts = upload_tiles(c, c->tiles);
+            if (ts != NNP_OK) return ts;
+            HIP_TRY(c, hipMemset(c->S.work, 0, sizeof(int) * c->n));
+        }
     }
     if (vel) {
         if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before velocities");
@@ -849,12 +931,18 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         HIP_TRY(c, enqueue_compute(c, true));
         c->forces_current = true;
     }
+    const int B = std::min<int>(nsteps, 100);
     if (!use_graph || c->stream == nullptr) {
-        HIP_TRY(c, enqueue_steps(c, dt, nsteps, true));
+        // blocks of at most 100 steps, as with graphs (tile balancing between
+        // blocks gives graph and eager runs the same trajectory)
+        for (int left = nsteps; left > 0; left -= B) {
+            const nnp_status bs = rebalance_tiles(c);
+            if (bs != NNP_OK) return bs;
+            HIP_TRY(c, enqueue_steps(c, dt, std::min(left, B), true));
+        }
         c->kick_pending = true;
         return NNP_OK;
     }
-    const int B = std::min<int>(nsteps, 100);
     auto run_block = [&](int len) -> nnp_status {
         const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T);
         auto it = c->graphs.find(key);
@@ -877,7 +965,9 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
     int left = nsteps;
     while (left > 0) {
         const int len = left >= B ? B : left;
-        nnp_status s = run_block(len);
+        nnp_status s = rebalance_tiles(c);
+        if (s != NNP_OK) return s;
+        s = run_block(len);
         if (s != NNP_OK) return s;
         left -= len;
     }
@@ -1074,6 +1164,10 @@ nnp_status nnp_time_steps(nnp_context* c, double dt, int32_t nsteps, double* ms)
     if (!c->forces_current) {
         HIP_TRY(c, enqueue_compute(c, true));
         c->forces_current = true;
+    }
+    {
+        const nnp_status bs = rebalance_tiles(c);  // as at the start of a block of nnp_step
+        if (bs != NNP_OK) return bs;
     }
     // per step: start / end of the evaluation kernel(s) and of the gather /
     // integration kernel, stamped by the dispatches themselves

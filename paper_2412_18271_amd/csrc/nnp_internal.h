@@ -42,7 +42,8 @@ constexpr int kRadMax = 160;  // radial entries per atom held in LDS
 constexpr int kAngMax = 96;   // angular entries per atom held in LDS
 constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits)
 constexpr int kRing = 4096;   // energy log ring (steps)
-constexpr int kXcds = 8;     // accelerator complex dies; workgroups go round-robin
+constexpr int kXcds = 8;
+constexpr int kTileCap = 16;  // largest atoms-per-tile (MFMA columns)     // accelerator complex dies; workgroups go round-robin
 
 // Per-element FP32 weight block (floats).  Forward dense layers read the
 // transposed matrices ([in][out], coalesced over outputs), the backward ones
@@ -115,7 +116,9 @@ struct Sys {
     const double* mass;
     const int* mol;
     const int2* mrange;  // [nmol * 4] internal index range of each element of a molecule
-    const int4* tiles;   // {first atom, count, element, 0}
+    const int4* tiles;      // {first atom of the initial tiling, count, element, 0}
+    const int* tile_atoms;  // [ntiles][kTileCap] atom in each column of a tile
+    int* work;              // [n] angular pairs + radial entries / 2 at the last evaluation
     int* nbr;
     int* ncnt;
     unsigned long long* facc;  // [n][4] fixed-point forces, zero between evaluations

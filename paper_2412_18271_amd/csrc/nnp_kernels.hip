@@ -74,8 +74,8 @@ __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
     __shared__ __attribute__((aligned(16))) FusedSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[blockIdx.x];
-    const int a = tile.x + wave;
     const bool act = wave < tile.y;
+    const int a = act ? S.tile_atoms[blockIdx.x * kTileCap + wave] : 0;
     const bool rb = rebuild_due(S.st, S.rebuild_every);
     Env& E = sm.env[wave];
     float* Grow = sm.G + wave * kLdG;
@@ -85,6 +85,7 @@ __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
             build_list_env(S, a, E);
         else
             load_env(S, a, E);
+        if (lane == 0) S.work[a] = E.nA * (E.nA - 1) / 2 + E.nR / 2;
     }
     for (int i = tid; i < T * kLdG; i += 64 * T) sm.G[i] = 0.f;
     for (int i = tid; i < T * 10 * kAccStride; i += 64 * T) sm.u.acc[i] = 0.f;
@@ -176,8 +177,8 @@ __global__ __launch_bounds__(64 * T) void k_eval_pooled(Sys S)
     __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[blockIdx.x];
-    const int a = tile.x + wave;
     const bool act = wave < tile.y;
+    const int a = act ? S.tile_atoms[blockIdx.x * kTileCap + wave] : 0;
     const bool rb = rebuild_due(S.st, S.rebuild_every);
     Env& E = sm.env[wave];
     float* Grow = sm.G + wave * kLdG;
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(64 * T) void k_eval_pooled(Sys S)
             build_list_env(S, a, E);
         else
             load_env(S, a, E);
+        if (lane == 0) S.work[a] = E.nA * (E.nA - 1) / 2 + E.nR / 2;
     }
     for (int i = tid; i < T * kLdG; i += 64 * T) sm.G[i] = 0.f;
     for (int i = tid; i < T * 320; i += 64 * T) sm.u.accI[i] = 0ull;
@@ -227,18 +229,19 @@ __global__ __launch_bounds__(64 * T) void k_mlp(Sys S)
     __shared__ float E[16];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[blockIdx.x];
+    const int* col = S.tile_atoms + blockIdx.x * kTileCap;
     for (int i = tid; i < T * kLdG; i += 64 * T) {
         const int t = i / kLdG, f = i % kLdG;
-        G[i] = (t < tile.y && f < kNumFeat) ? S.G[(size_t)(tile.x + t) * kNumFeat + f] : 0.f;
+        G[i] = (t < tile.y && f < kNumFeat) ? S.G[(size_t)col[t] * kNumFeat + f] : 0.f;
     }
     __syncthreads();
     run_mlp<T, MODE, GRAD>(S, tile.z, G, u, E, tid);
     __syncthreads();
-    if (wave < tile.y && lane == 0) S.Ei[tile.x + wave] = E[wave];
+    if (wave < tile.y && lane == 0) S.Ei[col[wave]] = E[wave];
     if (GRAD)
         for (int i = tid; i < T * kNumFeat; i += 64 * T) {
             const int t = i / kNumFeat, f = i % kNumFeat;
-            if (t < tile.y) S.dG[(size_t)(tile.x + t) * kNumFeat + f] = G[t * kLdG + f];
+            if (t < tile.y) S.dG[(size_t)col[t] * kNumFeat + f] = G[t * kLdG + f];
         }
 }
 
