@@ -288,6 +288,64 @@ __device__ __forceinline__ double atomic_read(double* p)
 // One thread per atom.
 constexpr int kGatherThreads = 256;
 
+// Forces of atom a from its fixed-point sums (cleared for the next
+// evaluation), velocity-Verlet update by mode, its energies and flags.
+__device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, int mode, int forces, double& e,
+                                               double& k, bool& moved, bool& bad)
+{
+    unsigned long long* fa = S.facc + 4 * (size_t)a;
+    const unsigned long long qx = fa[0], qy = fa[1], qz = fa[2];
+    fa[0] = 0ull;
+    fa[1] = 0ull;
+    fa[2] = 0ull;
+    const double fx = (double)(long long)qx * (1.0 / kFixScale);
+    const double fy = (double)(long long)qy * (1.0 / kFixScale);
+    const double fz = (double)(long long)qz * (1.0 / kFixScale);
+    double4 v = S.vel[a];
+    const double ki = S.kinv[a];
+    e = (double)S.Ei[a];
+    if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
+    if (mode >= 1) {
+        v.x += 0.5 * dt * ki * fx;
+        v.y += 0.5 * dt * ki * fy;
+        v.z += 0.5 * dt * ki * fz;
+    }
+    k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
+    if (mode == 2) {
+        double4 p = S.pos[a];
+        const float4 r0 = S.ref[a];
+        v.x += 0.5 * dt * ki * fx;
+        v.y += 0.5 * dt * ki * fy;
+        v.z += 0.5 * dt * ki * fz;
+        p.x += dt * v.x;
+        p.y += dt * v.y;
+        p.z += dt * v.z;
+        S.pos[a] = p;
+        const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
+        moved = moved || dx * dx + dy * dy + dz * dz > S.half_skin2;
+    }
+    if (mode >= 1) S.vel[a] = v;
+    bad = bad || !isfinite(e);
+}
+
+// New step state after an evaluation (nstep, age, valid, rb as the
+// evaluation saw them) and its energies; one thread.
+__device__ __forceinline__ void finish_step(const Sys& S, int mode, int nstep, int age, int valid, bool rb)
+{
+    StepState* st = S.st;
+    atomicAdd((unsigned long long*)&st->n_eval, 1ull);
+    if (rb) {
+        atomicAdd((unsigned long long*)&st->n_rebuild, 1ull);
+        if (valid && age < S.rebuild_every) atomicAdd((unsigned long long*)&st->n_forced, 1ull);
+        st->lists_valid = 1;
+    }
+    st->age = rb ? 1 : age + 1;
+    st->viol[nstep & 1] = 0;
+    st->last_slot = mode >= 1 ? nstep + 1 : nstep;
+    if (mode >= 1) st->step = nstep + 1;
+    st->done = 0u;
+}
+
 __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, double dt, int mode, int forces)
 {
     __shared__ int last;
@@ -301,40 +359,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, doub
     int mol = -1;
     bool moved = false, bad = false;
     if (a < S.n) {
-        unsigned long long* fa = S.facc + 4 * (size_t)a;
-        const unsigned long long qx = fa[0], qy = fa[1], qz = fa[2];
-        fa[0] = 0ull;
-        fa[1] = 0ull;
-        fa[2] = 0ull;
-        const double fx = (double)(long long)qx * (1.0 / kFixScale);
-        const double fy = (double)(long long)qy * (1.0 / kFixScale);
-        const double fz = (double)(long long)qz * (1.0 / kFixScale);
-        double4 v = S.vel[a];
-        const double ki = S.kinv[a];
-        e = (double)S.Ei[a];
         mol = S.mol[a];
-        if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
-        if (mode >= 1) {
-            v.x += 0.5 * dt * ki * fx;
-            v.y += 0.5 * dt * ki * fy;
-            v.z += 0.5 * dt * ki * fz;
-        }
-        k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
-        if (mode == 2) {
-            double4 p = S.pos[a];
-            const float4 r0 = S.ref[a];
-            v.x += 0.5 * dt * ki * fx;
-            v.y += 0.5 * dt * ki * fy;
-            v.z += 0.5 * dt * ki * fz;
-            p.x += dt * v.x;
-            p.y += dt * v.y;
-            p.z += dt * v.z;
-            S.pos[a] = p;
-            const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
-            moved = dx * dx + dy * dy + dz * dz > S.half_skin2;
-        }
-        if (mode >= 1) S.vel[a] = v;
-        bad = !isfinite(e);
+        integrate_atom(S, a, dt, mode, forces, e, k, moved, bad);
     }
     if (__ballot(moved) != 0ull && lane == 0) atomicOr(&st->viol[(nstep + 1) & 1], 1);
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&st->nonfinite, 1);
@@ -380,20 +406,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, doub
         __hip_atomic_store(&S.Eacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&S.Kacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (tid == 0) {
-        // new values from the state read at entry: no read-modify-write
-        atomicAdd((unsigned long long*)&st->n_eval, 1ull);
-        if (rb) {
-            atomicAdd((unsigned long long*)&st->n_rebuild, 1ull);
-            if (valid && age < S.rebuild_every) atomicAdd((unsigned long long*)&st->n_forced, 1ull);
-            st->lists_valid = 1;
-        }
-        st->age = rb ? 1 : age + 1;
-        st->viol[nstep & 1] = 0;
-        st->last_slot = eval_index;
-        if (mode >= 1) st->step = nstep + 1;
-        st->done = 0u;
-    }
+    if (tid == 0) finish_step(S, mode, nstep, age, valid, rb);  // from the state read at entry
 }
 
 // First half kick and drift of a step (starts a block of steps).
