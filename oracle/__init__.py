@@ -57,6 +57,13 @@ def _load():
     lib.oracle_forces_on.argtypes = [i, P(d), P(i), P(f), i, P(i), P(d)]
     lib.oracle_vv.restype = None
     lib.oracle_vv.argtypes = [i, P(d), P(d), P(d), P(i), P(f), i, d, i, P(d), P(d)]
+    u64, i64 = ctypes.c_uint64, ctypes.c_int64
+    lib.oracle_philox4x64.restype = None
+    lib.oracle_philox4x64.argtypes = [P(u64), P(u64), P(u64)]
+    lib.oracle_langevin_noise.restype = None
+    lib.oracle_langevin_noise.argtypes = [u64, i64, i64, P(d)]
+    lib.oracle_langevin.restype = None
+    lib.oracle_langevin.argtypes = [i, P(d), P(d), P(d), P(i), P(f), i, d, i, d, d, u64, i64, i64, P(d), P(d)]
     lib.oracle_threads.restype = i
     lib.oracle_threads.argtypes = []
     lib.oracle_set_threads.restype = None
@@ -162,6 +169,45 @@ def vv(pos, vel, masses, species, weights, dt: float, nsteps: int, model: int = 
                   _ptr(m, ctypes.c_double), _ptr(s, ctypes.c_int), _ptr(w, ctypes.c_float),
                   int(model), float(dt), int(nsteps), _ptr(U, ctypes.c_double),
                   _ptr(K, ctypes.c_double))
+    return x, v, U, K
+
+
+def philox4x64(counter, key) -> np.ndarray:
+    """Philox4x64-10 block of a 4-word counter under a 2-word key (O10)."""
+    lib = _load()
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib.oracle_philox4x64(_ptr(c, ctypes.c_uint64), _ptr(k, ctypes.c_uint64), _ptr(out, ctypes.c_uint64))
+    return out
+
+
+def langevin_noise(seed: int, atom: int, step: int) -> np.ndarray:
+    """The three standard normal values of caller atom `atom` in step `step` (O10)."""
+    lib = _load()
+    z = np.zeros(3, np.float64)
+    lib.oracle_langevin_noise(int(seed), int(atom), int(step), _ptr(z, ctypes.c_double))
+    return z
+
+
+def langevin(pos, vel, masses, species, weights, dt: float, nsteps: int, temperature: float,
+             friction: float, seed: int, first_index: int = 0, first_step: int = 0, model: int = 0):
+    """BAOAB Langevin dynamics (O9): friction in 1/ps, temperature in K.
+    model 0 = network, 1 = harmonic sum(x^2), 2 = no force.
+    Returns (x, v, U[nsteps+1], K[nsteps+1])."""
+    lib = _load()
+    x = _pos(pos).copy()
+    v = _pos(vel).copy()
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    s = _sp(species)
+    w = _w(weights) if weights is not None else np.zeros(1, np.float32)
+    U = np.zeros(nsteps + 1, np.float64)
+    K = np.zeros(nsteps + 1, np.float64)
+    lib.oracle_langevin(x.shape[0], _ptr(x, ctypes.c_double), _ptr(v, ctypes.c_double),
+                        _ptr(m, ctypes.c_double), _ptr(s, ctypes.c_int), _ptr(w, ctypes.c_float),
+                        int(model), float(dt), int(nsteps), float(temperature), float(friction),
+                        int(seed), int(first_index), int(first_step), _ptr(U, ctypes.c_double),
+                        _ptr(K, ctypes.c_double))
     return x, v, U, K
 
 

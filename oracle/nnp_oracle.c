@@ -32,10 +32,24 @@
  *   O8  velocity Verlet: v += dt/2 kappa F/m; x += dt v; F = F(x);
  *       v += dt/2 kappa F/m; kappa = 9.64853321e-3 A fs^-2 per eV A^-1 amu^-1
  *
- * The harmonic test model E = sum(x^2) (the paper's Model42 example) is
- * provided as a second force model for the integrator.
+ *   O9  Langevin dynamics (the thermostatted runs of the Results section,
+ *       friction 0.1 ps^-1), BAOAB splitting (Leimkuhler and Matthews,
+ *       J. Chem. Phys. 138, 174102 (2013)), velocities at whole steps:
+ *       v += dt/2 kappa F/m; x += dt/2 v;
+ *       v = a v + sqrt((1 - a^2) kB T kappa / m) z,   a = exp(-gamma dt);
+ *       x += dt/2 v; F = F(x); v += dt/2 kappa F/m
+ *   O10 noise z of atom c (caller index) in the step that starts at step
+ *       count s: Philox4x64-10 (Salmon et al., SC'11) of the counter
+ *       (c, s, 0, 0) under the key (seed, 0); each 64-bit word w gives
+ *       u = (floor(w / 2^11) + 1/2) 2^-53, and Box-Muller turns (u0, u1),
+ *       (u2, u3) into sqrt(-2 ln u0) (cos, sin)(2 pi u1) and
+ *       sqrt(-2 ln u2) cos(2 pi u3): z = those three values for x, y, z
+ *
+ * The harmonic test model E = sum(x^2) (the paper's Model42 example) and a
+ * force-free model are provided as further force models for the integrators.
  */
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -60,6 +74,7 @@ static const double ZETA = 32.0;
 static const double COS_SCALE = 0.95;
 static const double CELU_ALPHA = 0.1;
 static const double KAPPA = 9.64853321e-3;
+static const double KB = 8.617333262e-5; /* eV / K */
 
 #define PER_ELEMENT (H1 * NFEAT + H1 + H2 * H1 + H2 + H3 * H2 + H3 + H3 + 1)
 
@@ -447,6 +462,96 @@ void oracle_vv(int n, double* x, double* v, const double* m, const int* sp, cons
         E = model == 1 ? harmonic(n, x, F) : oracle_energy_forces(n, x, sp, weights, NULL, F);
         for (int i = 0; i < n; ++i)
             for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * KAPPA * F[3 * i + c] / m[i];
+        if (U) U[s] = E;
+        if (K) K[s] = kinetic(n, v, m);
+    }
+    free(F);
+}
+
+/* Force model of the integrators: 0 network, 1 harmonic sum(x^2), 2 none. */
+static double model_forces(int model, int n, const double* x, const int* sp, const float* weights, double* F)
+{
+    if (model == 1) return harmonic(n, x, F);
+    if (model == 2) {
+        memset(F, 0, sizeof(double) * 3 * (size_t)n);
+        return 0.0;
+    }
+    return oracle_energy_forces(n, x, sp, weights, NULL, F);
+}
+
+/* O10: Philox4x64-10.  Each of the ten rounds multiplies counter words 0 and
+ * 2 by the two round constants (full 128-bit products), swaps the halves
+ * across the two lanes and mixes in the key; the key advances by the two
+ * Weyl constants between rounds. */
+void oracle_philox4x64(const uint64_t* ctr, const uint64_t* key, uint64_t* out)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        const unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* O10: the three standard normal values of atom `atom` in step `step`. */
+void oracle_langevin_noise(uint64_t seed, int64_t atom, int64_t step, double* z)
+{
+    const uint64_t ctr[4] = {(uint64_t)atom, (uint64_t)step, 0, 0};
+    const uint64_t key[2] = {seed, 0};
+    uint64_t w[4];
+    oracle_philox4x64(ctr, key, w);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = ((double)(w[q] >> 11) + 0.5) * ldexp(1.0, -53);
+    const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    z[0] = r0 * cos(2.0 * PI * u[1]);
+    z[1] = r0 * sin(2.0 * PI * u[1]);
+    z[2] = r1 * cos(2.0 * PI * u[3]);
+}
+
+/* O9: nsteps of BAOAB Langevin dynamics on one molecule, in place on x and v.
+ * Atom i draws its noise as caller index first_index + i; the first step
+ * taken is step count first_step.  friction in 1/ps, temperature in K.
+ * U and K as for oracle_vv. */
+void oracle_langevin(int n, double* x, double* v, const double* m, const int* sp, const float* weights, int model,
+                     double dt, int nsteps, double temperature, double friction, uint64_t seed, int64_t first_index,
+                     int64_t first_step, double* U, double* K)
+{
+    double* F = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    const double a = exp(-friction * 1e-3 * dt);
+    double E = model_forces(model, n, x, sp, weights, F);
+    if (U) U[0] = E;
+    if (K) K[0] = kinetic(n, v, m);
+    for (int s = 1; s <= nsteps; ++s) {
+        for (int i = 0; i < n; ++i) {
+            double z[3];
+            oracle_langevin_noise(seed, first_index + i, first_step + s - 1, z);
+            const double sigma = sqrt((1.0 - a * a) * KB * temperature * KAPPA / m[i]);
+            for (int c = 0; c < 3; ++c) {
+                double* vi = &v[3 * i + c];
+                double* xi = &x[3 * i + c];
+                *vi += 0.5 * dt * KAPPA * F[3 * i + c] / m[i]; /* B */
+                *xi += 0.5 * dt * *vi;                         /* A */
+                *vi = a * *vi + sigma * z[c];                  /* O */
+                *xi += 0.5 * dt * *vi;                         /* A */
+            }
+        }
+        E = model_forces(model, n, x, sp, weights, F);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * KAPPA * F[3 * i + c] / m[i]; /* B */
         if (U) U[s] = E;
         if (K) K[s] = kinetic(n, v, m);
     }

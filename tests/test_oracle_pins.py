@@ -312,3 +312,99 @@ def test_vv_nve_network_drift_second_order(make_system):
         amp.append(np.max(np.abs(H - H[0])))
     assert amp[0] < 1e-3
     assert 3.0 < amp[0] / amp[1] < 5.0
+
+
+# ------------------------------------------------- O9/O10 Langevin (BAOAB)
+
+KB = 8.617333262e-5
+
+
+@pytest.mark.parametrize("ctr,key", [
+    ([1, 0, 0, 0], [0, 0]),
+    ([42, 7, 3, 9], [123456789, 987654321]),
+    ([2**63 + 5, 2**64 - 1, 17, 2**40], [2**64 - 1, 2**32 + 1]),
+])
+def test_philox_matches_numpy(ctr, key):
+    """Philox4x64-10 equals numpy's independent implementation (which
+    advances its counter by one before producing a block)."""
+    g = np.random.Philox(counter=np.array([ctr[0] - 1] + ctr[1:], np.uint64), key=np.array(key, np.uint64))
+    want = g.random_raw(4)
+    np.testing.assert_array_equal(oracle.philox4x64(ctr, key), want)
+
+
+def test_langevin_noise_is_independent_standard_normal():
+    """Box-Muller values over 8,000 (atom, step) counters: moments of N(0, 1),
+    Kolmogorov-Smirnov against the normal CDF, no correlation between the
+    three components or between consecutive steps, a different seed gives
+    different values."""
+    from scipy import stats
+    z = np.array([oracle.langevin_noise(11, a, s) for a in range(200) for s in range(40)])
+    assert z.shape == (8000, 3)
+    flat = z.ravel()
+    assert abs(flat.mean()) < 0.03
+    assert abs(flat.var() - 1.0) < 0.03
+    assert abs(stats.kurtosis(flat, fisher=False) - 3.0) < 0.15
+    assert stats.kstest(flat, "norm").pvalue > 1e-3
+    c = np.corrcoef(z.T)
+    assert np.abs(c - np.eye(3)).max() < 0.05
+    zz = z.reshape(200, 40, 3)
+    lag = (zz[:, 1:] * zz[:, :-1]).mean()
+    assert abs(lag) < 0.03
+    assert not np.allclose(oracle.langevin_noise(12, 0, 0), oracle.langevin_noise(11, 0, 0))
+    assert np.array_equal(oracle.langevin_noise(11, 5, 9), zz[5, 9])
+
+
+def test_langevin_without_friction_is_velocity_verlet(make_system):
+    """friction 0: a = 1 and no noise, and the two half drifts make one whole
+    drift, so BAOAB is velocity Verlet (to rounding)."""
+    s = make_system("mol22")
+    x1, v1, U1, K1 = oracle.langevin(s.pos, s.vel, s.masses, s.species, s.weights, 0.5, 100, 300.0, 0.0, 3)
+    x2, v2, U2, K2 = oracle.vv(s.pos, s.vel, s.masses, s.species, s.weights, 0.5, 100)
+    np.testing.assert_allclose(x1, x2, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(U1 + K1, U2 + K2, rtol=0, atol=1e-9)
+
+
+def test_langevin_free_particles_are_ornstein_uhlenbeck():
+    """No forces: v_{n+1} = a v_n + sqrt(1 - a^2) sigma z exactly, so from
+    v = 0 the variance after n steps is (1 - a^{2n}) kT kappa / m, and the
+    stationary lag-1 correlation is a = exp(-gamma dt).  Tolerances are
+    four standard errors of the 18,000-value estimates."""
+    n, dt, T, fric = 6000, 0.5, 300.0, 50.0
+    rng = _rng(21)
+    m = rng.uniform(1.0, 16.0, n)
+    x0 = rng.normal(size=(n, 3))
+    v0 = np.zeros((n, 3))
+    a = math.exp(-fric * 1e-3 * dt)
+    sp = np.zeros(n, np.int32)
+    x, v, _, _ = oracle.langevin(x0, v0, m, sp, None, dt, 40, T, fric, 5, model=2)
+    u = v / np.sqrt(KB * T * KAPPA / m)[:, None]
+    assert u.var() == pytest.approx(1.0 - a ** 80, abs=0.037)
+    x, v, _, _ = oracle.langevin(x, v, m, sp, None, dt, 160, T, fric, 5, first_step=40, model=2)
+    _, v2, _, _ = oracle.langevin(x, v, m, sp, None, dt, 1, T, fric, 5, first_step=200, model=2)
+    u, u2 = (w / np.sqrt(KB * T * KAPPA / m)[:, None] for w in (v, v2))
+    assert u.var() == pytest.approx(1.0, abs=0.042)
+    assert (u * u2).mean() / (u * u).mean() == pytest.approx(a, abs=0.007)
+
+
+@pytest.mark.parametrize("dt", [2.0, 7.0])
+def test_langevin_harmonic_configurations_exact(dt):
+    """BAOAB samples the configurational Boltzmann distribution of a harmonic
+    potential exactly at any stable step (Leimkuhler and Matthews 2013): on
+    E = sum x^2, <x^2> = kT/2 per coordinate even at omega dt ~ 1, where
+    splittings in another order are off by (omega dt / 2)^2 ~ 25 %.  The
+    whole-step velocities carry the known bias <K> = 3/2 n kT (1 - (omega dt)^2 / 4)."""
+    n, T, fric = 4000, 300.0, 20.0
+    rng = _rng(22)
+    m = np.ones(n)
+    x = rng.normal(size=(n, 3)) * 0.1
+    v = np.zeros((n, 3))
+    sp = np.zeros(n, np.int32)
+    x, v, _, _ = oracle.langevin(x, v, m, sp, None, dt, 300, T, fric, 7, model=1)
+    xs, ks = [], []
+    for blk in range(10):
+        x, v, _, K = oracle.langevin(x, v, m, sp, None, dt, 30, T, fric, 7, first_step=300 + 30 * blk, model=1)
+        xs.append((x ** 2).mean())
+        ks.append(K[-1])
+    wdt = math.sqrt(2.0 * KAPPA) * dt
+    assert np.mean(xs) / (KB * T / 2) == pytest.approx(1.0, abs=0.02)
+    assert np.mean(ks) / (1.5 * n * KB * T) == pytest.approx(1.0 - wdt ** 2 / 4, abs=0.02)
