@@ -167,6 +167,28 @@ def run_variant(P, s, dtype, path, steps, warmup, refs):
         ctx.close()
 
 
+def langevin_leg(P, s, dtype, path, steps, warmup):
+    """The paper's timed integrator: Langevin dynamics (BAOAB) at 300 K with a
+    friction of 0.1 ps^-1, same graph-replayed blocks as the NVE run."""
+    ctx = P.Context.from_system(s, dtype=dtype, path=path)
+    try:
+        ctx.set_state(s.pos, s.vel)
+        ctx.set_thermostat(300.0, 0.1, 0)
+        ctx.step(DT_FS, warmup, graph=True)
+        ctx.stats()
+        t0 = time.perf_counter()
+        ctx.step(DT_FS, steps, graph=True)
+        ctx.stats()
+        t1 = time.perf_counter()
+        _, K = ctx.energy_log(min(steps, 4096))
+        return {"dtype": dtype, "path": path, "temperature_K": 300.0, "friction_per_ps": 0.1,
+                "steps_per_s": steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+                "ns_per_day": steps / (t1 - t0) * DT_FS * 86400 / 1e6,
+                "kinetic_temperature_K": float(2.0 * K[:, 0].mean() / (3 * s.n_atoms * 8.617333262e-5))}
+    finally:
+        ctx.close()
+
+
 def batch_leg(P, steps, warmup):
     """256 molecules of 10-300 atoms: molecule-steps/s of one batched context
     (one evaluation launch per step for all molecules, graph-replayed) against
@@ -497,6 +519,9 @@ def main():
         "variants": res,
         "roofline": roofline,
     }
+    log("langevin")
+    out["langevin"] = langevin_leg(P, s, best["dtype"], best["path"], args.steps, args.warmup)
+    log("  ", json.dumps(out["langevin"]))
     if not args.no_batch:
         log("batch256")
         out["batch256"] = batch_leg(P, 100, 20)

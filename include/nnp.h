@@ -7,7 +7,8 @@
  * minus its gradient; the explicit-force provider variant returns both):
  *
  *     nnp_create(params)  ->  nnp_compute(positions, box)  ->  energy, forces
- *                         ->  nnp_step(dt, n)              (NVE velocity Verlet)
+ *                         ->  nnp_step(dt, n)              (NVE velocity Verlet, or
+ *                                                           Langevin: nnp_set_thermostat)
  *
  * The model is a symmetry-function network potential:
  *   - pair sets within 5.2 A (radial) and 3.5 A (angular), gas phase (no box);
@@ -181,6 +182,26 @@ nnp_status nnp_get_state(nnp_context* ctx, double* pos, double* vel, double* for
  * first use for the given block length and dt).  Returns after enqueueing;
  * nnp_get_state / nnp_energy_log synchronise. */
 nnp_status nnp_step(nnp_context* ctx, double dt_fs, int32_t n_steps, int32_t use_graph);
+
+/* Thermostat of nnp_step (the paper times its runs with Langevin dynamics at
+ * a friction of 0.1 ps^-1, Results section).  friction_per_ps > 0 makes every
+ * following step a BAOAB Langevin step (Leimkuhler and Matthews 2013):
+ *   v += dt/2 kappa F/m;  x += dt/2 v;
+ *   v = a v + sqrt((1 - a^2) kB T kappa / m) z,  a = exp(-friction dt);
+ *   x += dt/2 v;  F = F(x);  v += dt/2 kappa F/m,
+ * with velocities (and the logged kinetic energy) at whole steps.  z holds
+ * three standard normal values per atom and step: Philox4x64-10 (Salmon et al.,
+ * SC'11) of the counter (caller atom index, step count, 0, 0) under the key
+ * (seed, 0), each 64-bit word w taken as u = (floor(w / 2^11) + 1/2) 2^-53, and
+ * Box-Muller on (u0, u1) and (u2, u3) giving sqrt(-2 ln u0) cos(2 pi u1),
+ * sqrt(-2 ln u0) sin(2 pi u1), sqrt(-2 ln u2) cos(2 pi u3).  The step count is
+ * the number of steps the context has taken (nnp_stats), so a trajectory is
+ * reproducible from (state, step count, seed) and independent of graphs.
+ *   temperature_K    >= 0 (kB = 8.617333262e-5 eV/K);
+ *   friction_per_ps  >= 0; 0 (the default) restores NVE velocity Verlet;
+ *   seed             any value.
+ * Non-finite or negative values: NNP_ERR_ARG, settings unchanged. */
+nnp_status nnp_set_thermostat(nnp_context* ctx, double temperature_K, double friction_per_ps, uint64_t seed);
 
 /* Potential and kinetic energy of the last min(count, steps done, ring size)
  * steps, oldest first: U and K are [count][n_molecules] double.  Returns the

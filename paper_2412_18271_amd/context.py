@@ -133,6 +133,11 @@ class Context:
     def step(self, dt: float, n_steps: int, graph: bool = True):
         self._check(self._lib.nnp_step(self._h, float(dt), int(n_steps), 1 if graph else 0))
 
+    def set_thermostat(self, temperature: float = 300.0, friction: float = 0.1, seed: int = 0):
+        """Langevin dynamics (BAOAB) for the following steps: temperature in K,
+        friction in 1/ps; friction 0 restores NVE velocity Verlet."""
+        self._check(self._lib.nnp_set_thermostat(self._h, float(temperature), float(friction), int(seed)))
+
     def energy_log(self, count: int):
         m = self.n_molecules
         U = np.zeros((count, m))

@@ -72,7 +72,8 @@ struct nnp_context {
     bool forces_current = false;
     bool kick_pending = false;  // previous block ended after a completed step (mode 1)
     int diff_state = 0;         // 0: none, 1: energy evaluated (recompute), 2: energy + kept G, dE/dG
-    std::map<std::tuple<int, double, int, int, int>, hipGraphExec_t> graphs;
+    // captured MD blocks by (steps, dt, path, dtype, tile, friction, kT, seed)
+    std::map<std::tuple<int, double, int, int, int, double, double, unsigned long long>, hipGraphExec_t> graphs;
     // pinned staging
     double* h_stage = nullptr;
     size_t h_stage_bytes = 0;
@@ -944,7 +945,7 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         return NNP_OK;
     }
     auto run_block = [&](int len) -> nnp_status {
-        const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T);
+        const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T, c->S.gamma, c->S.kT, c->S.seed);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipGraph_t g;
@@ -972,6 +973,19 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         left -= len;
     }
     c->kick_pending = true;
+    return NNP_OK;
+}
+
+nnp_status nnp_set_thermostat(nnp_context* c, double temperature, double friction, uint64_t seed)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!(temperature >= 0.0) || !std::isfinite(temperature))
+        return fail(c, NNP_ERR_ARG, "temperature must be finite and >= 0");
+    if (!(friction >= 0.0) || !std::isfinite(friction)) return fail(c, NNP_ERR_ARG, "friction must be finite and >= 0");
+    c->S.gamma = friction * 1e-3;           // 1/ps -> 1/fs
+    c->S.kT = 8.617333262e-5 * temperature;  // Boltzmann constant in eV/K
+    c->S.seed = seed;
+    c->err.clear();
     return NNP_OK;
 }
 

@@ -42,8 +42,8 @@ constexpr int kRadMax = 160;  // radial entries per atom held in LDS
 constexpr int kAngMax = 96;   // angular entries per atom held in LDS
 constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits)
 constexpr int kRing = 4096;   // energy log ring (steps)
-constexpr int kXcds = 8;
-constexpr int kTileCap = 16;  // largest atoms-per-tile (MFMA columns)     // accelerator complex dies; workgroups go round-robin
+constexpr int kXcds = 8;      // accelerator complex dies; workgroups go round-robin
+constexpr int kTileCap = 16;  // largest atoms-per-tile (MFMA columns)
 
 // Per-element FP32 weight block (floats).  Forward dense layers read the
 // transposed matrices ([in][out], coalesced over outputs), the backward ones
@@ -112,6 +112,10 @@ struct Sys {
     double4* vel;
     double4* frc;
     float4* ref;
+    // Langevin dynamics (BAOAB) of nnp_step; gamma == 0 selects velocity Verlet
+    double gamma;        // friction (1/fs)
+    double kT;           // thermostat temperature (eV)
+    unsigned long long seed;  // Philox key of the thermostat noise
     const double* kinv;  // kappa / m
     const double* mass;
     const int* mol;

@@ -290,20 +290,94 @@ constexpr int kGatherThreads = 256;
 
 // Forces of atom a from its fixed-point sums (cleared for the next
 // evaluation), velocity-Verlet update by mode, its energies and flags.
-__device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, int mode, int forces, double& e,
-                                               double& k, bool& moved, bool& bad)
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 64 x 64 -> 128-bit products on counter words 0 and 2, the high halves
+// crossed over and mixed with the key, the key advanced by two Weyl
+// increments between rounds.
+__device__ __forceinline__ void philox4x64_10(unsigned long long& c0, unsigned long long& c1,
+                                              unsigned long long& c2, unsigned long long& c3,
+                                              unsigned long long k0, unsigned long long k1)
+{
+    constexpr unsigned long long kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+    constexpr unsigned long long kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
+        const unsigned long long hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += kW0;
+        k1 += kW1;
+    }
+}
+
+// Thermostat noise of caller atom `atom` in the step that starts at step
+// count `step`: the Philox block of counter (atom, step, 0, 0) under key
+// (seed, 0), each word mapped to a uniform in (0, 1) with 53 bits, two
+// Box-Muller pairs, the first three values.
+__device__ __forceinline__ double3 langevin_noise(unsigned long long seed, int atom, int step)
+{
+    unsigned long long w0 = (unsigned long long)atom, w1 = (unsigned long long)step, w2 = 0ull, w3 = 0ull;
+    philox4x64_10(w0, w1, w2, w3, seed, 0ull);
+    const double ulp = 1.1102230246251565e-16;  // 2^-53
+    const double u0 = ((double)(w0 >> 11) + 0.5) * ulp, u1 = ((double)(w1 >> 11) + 0.5) * ulp;
+    const double u2 = ((double)(w2 >> 11) + 0.5) * ulp, u3 = ((double)(w3 >> 11) + 0.5) * ulp;
+    const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+    double s0, c0;
+    sincospi(2.0 * u1, &s0, &c0);
+    return make_double3(r0 * c0, r0 * s0, r1 * cospi(2.0 * u3));
+}
+
+// Position update of a step (velocities already kicked by dt/2): one drift of
+// dt, or with a thermostat the middle of a BAOAB step: drift dt/2,
+// Ornstein-Uhlenbeck velocity update v = a v + sqrt((1 - a^2) kT kappa / m) z
+// with a = exp(-gamma dt) and the step's noise z, drift dt/2.
+__device__ __forceinline__ void drift_atom(const Sys& S, double dt, double ki, double3 z, double4& p, double4& v)
+{
+    if (S.gamma > 0.0) {
+        p.x += 0.5 * dt * v.x;
+        p.y += 0.5 * dt * v.y;
+        p.z += 0.5 * dt * v.z;
+        const double la = exp(-S.gamma * dt);
+        const double sig = sqrt((1.0 - la * la) * S.kT * ki);
+        v.x = la * v.x + sig * z.x;
+        v.y = la * v.y + sig * z.y;
+        v.z = la * v.z + sig * z.z;
+        p.x += 0.5 * dt * v.x;
+        p.y += 0.5 * dt * v.y;
+        p.z += 0.5 * dt * v.z;
+    } else {
+        p.x += dt * v.x;
+        p.y += dt * v.y;
+        p.z += dt * v.z;
+    }
+}
+
+__device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, int mode, int forces, int nstep,
+                                               double& e, double& k, bool& moved, bool& bad)
 {
     unsigned long long* fa = S.facc + 4 * (size_t)a;
     const unsigned long long qx = fa[0], qy = fa[1], qz = fa[2];
+    double4 v = S.vel[a];
+    const double ki = S.kinv[a];
+    e = (double)S.Ei[a];
+    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    double3 z = make_double3(0.0, 0.0, 0.0);
+    if (mode == 2) {
+        p = S.pos[a];
+        r0 = S.ref[a];
+        // noise of the next step, computed while the loads above are in flight
+        if (S.gamma > 0.0) z = langevin_noise(S.seed, S.perm[a], nstep + 1);
+    }
     fa[0] = 0ull;
     fa[1] = 0ull;
     fa[2] = 0ull;
     const double fx = (double)(long long)qx * (1.0 / kFixScale);
     const double fy = (double)(long long)qy * (1.0 / kFixScale);
     const double fz = (double)(long long)qz * (1.0 / kFixScale);
-    double4 v = S.vel[a];
-    const double ki = S.kinv[a];
-    e = (double)S.Ei[a];
     if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
     if (mode >= 1) {
         v.x += 0.5 * dt * ki * fx;
@@ -312,14 +386,10 @@ __device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, i
     }
     k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
     if (mode == 2) {
-        double4 p = S.pos[a];
-        const float4 r0 = S.ref[a];
         v.x += 0.5 * dt * ki * fx;
         v.y += 0.5 * dt * ki * fy;
         v.z += 0.5 * dt * ki * fz;
-        p.x += dt * v.x;
-        p.y += dt * v.y;
-        p.z += dt * v.z;
+        drift_atom(S, dt, ki, z, p, v);
         S.pos[a] = p;
         const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
         moved = moved || dx * dx + dy * dy + dz * dz > S.half_skin2;
@@ -360,7 +430,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, doub
     bool moved = false, bad = false;
     if (a < S.n) {
         mol = S.mol[a];
-        integrate_atom(S, a, dt, mode, forces, e, k, moved, bad);
+        integrate_atom(S, a, dt, mode, forces, nstep, e, k, moved, bad);
     }
     if (__ballot(moved) != 0ull && lane == 0) atomicOr(&st->viol[(nstep + 1) & 1], 1);
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&st->nonfinite, 1);
@@ -409,7 +479,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, doub
     if (tid == 0) finish_step(S, mode, nstep, age, valid, rb);  // from the state read at entry
 }
 
-// First half kick and drift of a step (starts a block of steps).
+// First half kick and drift (or kick, half drift, thermostat, half drift)
+// of a step; starts a block of steps.
 __global__ __launch_bounds__(256) void k_kickdrift(Sys S, double dt)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -419,12 +490,11 @@ __global__ __launch_bounds__(256) void k_kickdrift(Sys S, double dt)
     double4 v = S.vel[a];
     double4 p = S.pos[a];
     const double ki = S.kinv[a];
+    const double3 z = S.gamma > 0.0 ? langevin_noise(S.seed, S.perm[a], nstep) : make_double3(0.0, 0.0, 0.0);
     v.x += 0.5 * dt * ki * f.x;
     v.y += 0.5 * dt * ki * f.y;
     v.z += 0.5 * dt * ki * f.z;
-    p.x += dt * v.x;
-    p.y += dt * v.y;
-    p.z += dt * v.z;
+    drift_atom(S, dt, ki, z, p, v);
     S.vel[a] = v;
     S.pos[a] = p;
     const float4 r0 = S.ref[a];
