@@ -220,8 +220,92 @@ def local_environment(pos, centre: int, radius: float) -> np.ndarray:
     return np.nonzero(d < radius)[0].astype(np.int64)
 
 
+KAPPA = 9.64853321e-3  # A fs^-2 per eV A^-1 amu^-1
+
+
+def periodic_images(pos, box, reach: float):
+    """Explicit periodic images of an orthorhombic box: the n atoms wrapped
+    into [0, L) first (in input order), then every translated copy (integer
+    multiples of the edges) lying closer than ``reach`` to the box.
+    Returns (positions, index of the original atom of each row)."""
+    p = _pos(pos)
+    L = np.asarray(box, dtype=np.float64).reshape(3)
+    n = p.shape[0]
+    w = p - L * np.floor(p / L)
+    k = [int(np.ceil(reach / L[d])) for d in range(3)]
+    xs, ids = [w], [np.arange(n)]
+    for sx in range(-k[0], k[0] + 1):
+        for sy in range(-k[1], k[1] + 1):
+            for sz in range(-k[2], k[2] + 1):
+                if sx == 0 and sy == 0 and sz == 0:
+                    continue
+                q = w + np.array([sx, sy, sz]) * L
+                out = np.maximum(0.0, np.maximum(-q, q - L))
+                keep = np.sqrt((out * out).sum(axis=1)) < reach
+                xs.append(q[keep])
+                ids.append(np.nonzero(keep)[0])
+    return np.concatenate(xs), np.concatenate(ids)
+
+
+def periodic_energy_forces(pos, species, weights, box, forces: bool = True):
+    """(E, E_i[n], F[n,3] or None) of the infinite periodic system built from
+    the orthorhombic box ``box`` (edges in A).  Explicit images, no minimum
+    image convention: E_i of an atom in the box is its gas-phase E_i among
+    all images within 5.2 A; the force on atom a is minus the derivative of
+    the energies of every atom of the crystal with respect to x_a alone
+    (moving a together with its images changes sum_i E_i over the box by
+    exactly that amount, by translation symmetry), i.e. the gather-form force
+    on a among all images within 10.4 A, each of whose energies is complete."""
+    sp = _sp(species)
+    n = sp.shape[0]
+    x5, i5 = periodic_images(pos, box, RC_RAD)
+    _, Ei, _ = energy_forces(x5, sp[i5], weights, forces=False)
+    Ei = Ei[:n].copy()
+    F = None
+    if forces:
+        x10, i10 = periodic_images(pos, box, 2.0 * RC_RAD)
+        F = forces_on(x10, sp[i10], weights, np.arange(n))
+    return float(Ei.sum()), Ei, F
+
+
+def periodic_local_environment(pos, box, centre: int, radius: float):
+    """Atoms whose nearest image lies closer than ``radius`` to atom ``centre``
+    (radius <= half the shortest edge, so the nearest image is the only one),
+    the centre included.  Returns (indices ascending, positions of those
+    nearest images, the centre at its own position)."""
+    p = _pos(pos)
+    L = np.asarray(box, dtype=np.float64).reshape(3)
+    assert radius <= 0.5 * L.min()
+    d = p - p[centre]
+    d -= L * np.round(d / L)
+    idx = np.nonzero(np.sqrt((d * d).sum(axis=1)) < radius)[0]
+    return idx, p[centre] + d[idx]
+
+
+def periodic_vv(pos, vel, masses, species, weights, box, dt: float, nsteps: int):
+    """Velocity Verlet (O8) in the periodic box; positions stay unwrapped.
+    Returns (x, v, U[nsteps+1], K[nsteps+1])."""
+    x = _pos(pos).copy()
+    v = _pos(vel).copy()
+    m = np.asarray(masses, dtype=np.float64)[:, None]
+    E, _, F = periodic_energy_forces(x, species, weights, box)
+    U, K = [E], [0.5 * (m * v * v).sum() / KAPPA]
+    for _ in range(nsteps):
+        v += 0.5 * dt * KAPPA * F / m
+        x += dt * v
+        E, _, F = periodic_energy_forces(x, species, weights, box)
+        v += 0.5 * dt * KAPPA * F / m
+        U.append(E)
+        K.append(0.5 * (m * v * v).sum() / KAPPA)
+    return x, v, np.array(U), np.array(K)
+
+
 def system_energy_forces(system, forces: bool = True):
-    """Per-molecule energies (M,), per-atom energies (N,), forces (N,3)."""
+    """Per-molecule energies (M,), per-atom energies (N,), forces (N,3);
+    a system with a box is one periodic molecule."""
+    if getattr(system, "box", None) is not None:
+        E, Ei, F = periodic_energy_forces(system.pos, system.species, system.weights, system.box, forces)
+        return np.array([E]), Ei, F
     M = system.n_molecules
     E = np.zeros(M)
     Ei = np.zeros(system.n_atoms)

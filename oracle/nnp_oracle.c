@@ -45,6 +45,10 @@
  *       (u2, u3) into sqrt(-2 ln u0) (cos, sin)(2 pi u1) and
  *       sqrt(-2 ln u2) cos(2 pi u3): z = those three values for x, y, z
  *
+ * Periodic orthorhombic boxes are handled in the Python wrapper by explicit
+ * periodic images around the box fed to these gas-phase routines (no minimum
+ * image convention), see periodic_energy_forces.
+ *
  * The harmonic test model E = sum(x^2) (the paper's Model42 example) and a
  * force-free model are provided as further force models for the integrators.
  */

@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs for the gas-phase NNP workloads.
+"""Seeded synthetic inputs for the NNP workloads (gas-phase clusters, molecule
+batches and periodic boxes).
 
 This module draws inputs only: atom positions, species, masses, initial
 velocities, molecule boundaries and network weights.  It holds none of the
@@ -17,6 +18,8 @@ from .generate import (  # noqa: F401
     composition_counts,
     rsa_cube,
     rsa_ball,
+    rsa_periodic,
+    box_edge,
     ball_radius,
     maxwell_boltzmann,
     xavier_weights,

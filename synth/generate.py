@@ -63,6 +63,7 @@ class System:
     mol_offsets: np.ndarray  # (M + 1,) int32; molecule m is [off[m], off[m+1])
     weights: np.ndarray      # (N_WEIGHTS,) float32
     meta: dict
+    box: Optional[np.ndarray] = None  # (3,) orthorhombic box edges (Angstrom); None = gas phase
 
     @property
     def n_atoms(self) -> int:
@@ -96,18 +97,19 @@ def ball_radius(n: int, density: float = DENSITY) -> float:
     return (3.0 * n / (4.0 * math.pi * density)) ** (1.0 / 3.0)
 
 
-def _rsa(n: int, draw, rng, d_min: float, batch: int) -> np.ndarray:
-    """Random sequential addition; ``draw(rng, k)`` returns k candidates."""
+def _rsa(n: int, draw, rng, d_min: float, batch: int, boxsize=None) -> np.ndarray:
+    """Random sequential addition; ``draw(rng, k)`` returns k candidates.
+    With ``boxsize`` distances are taken between nearest periodic images."""
     placed = np.empty((0, 3), dtype=np.float64)
     while placed.shape[0] < n:
         cand = draw(rng, batch)
         if placed.shape[0]:
-            tree = cKDTree(placed)
+            tree = cKDTree(placed, boxsize=boxsize)
             near = tree.query_ball_point(cand, r=d_min, return_length=True)
             cand = cand[near == 0]
         # resolve conflicts inside the batch in draw order
         if cand.shape[0] > 1:
-            pairs = cKDTree(cand).query_pairs(d_min, output_type="ndarray")
+            pairs = cKDTree(cand, boxsize=boxsize).query_pairs(d_min, output_type="ndarray")
             if pairs.shape[0]:
                 later = {}
                 for a, b in pairs:
@@ -129,6 +131,20 @@ def rsa_cube(n: int, edge: float, seed: int, d_min: float = MIN_SEP) -> np.ndarr
         return r.uniform(0.0, edge, size=(k, 3))
 
     return _rsa(n, draw, rng, d_min, batch=max(64, n))
+
+
+def box_edge(n: int, density: float = DENSITY) -> float:
+    return (n / density) ** (1.0 / 3.0)
+
+
+def rsa_periodic(n: int, edge: float, seed: int, d_min: float = MIN_SEP) -> np.ndarray:
+    """RSA of ``n`` atoms in [0, edge)^3 with periodic minimum separation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def draw(r, k):
+        return r.uniform(0.0, edge, size=(k, 3))
+
+    return _rsa(n, draw, rng, d_min, batch=max(256, min(n, 32768)), boxsize=edge)
 
 
 def rsa_ball(n: int, seed: int, density: float = DENSITY, d_min: float = MIN_SEP) -> np.ndarray:
@@ -197,6 +213,19 @@ def _single(name: str, n: int, pos_seed: int, vel_seed: int, w_seed: int,
     return System(name, pos, species, masses, vel, off, xavier_weights(w_seed), meta)
 
 
+def _periodic(name: str, n: int, pos_seed: int, vel_seed: int, w_seed: int) -> System:
+    species = species_block(composition_counts(n))
+    L = box_edge(n)
+    pos = rsa_periodic(n, L, pos_seed)
+    masses = MASSES_AMU[species]
+    off = np.array([0, n], dtype=np.int32)
+    vel = maxwell_boltzmann(masses, off, vel_seed)
+    meta = {"pos_seed": pos_seed, "vel_seed": vel_seed, "weight_seed": w_seed,
+            "region": "periodic cube L=%.3f A" % L}
+    return System(name, pos, species, masses, vel, off, xavier_weights(w_seed), meta,
+                  box=np.array([L, L, L]))
+
+
 def _batch(name: str, n_mol: int, size_seed: int, pos_seed0: int, vel_seed: int,
            w_seed: int) -> System:
     sizes = molecule_sizes(n_mol, size_seed)
@@ -229,6 +258,10 @@ CONFIGS: Dict[str, dict] = {
                      w_seed=0),
     # 100,000-atom droplet, ball R = 62.04 A
     "droplet100k": dict(kind="single", n=100000, pos_seed=41, vel_seed=42, w_seed=0),
+    # periodic cubes at the same density (condensed phase): L = 13.57, 29.24, 61.27 A
+    "box250": dict(kind="periodic", n=250, pos_seed=55, vel_seed=56, w_seed=0),
+    "box2500": dict(kind="periodic", n=2500, pos_seed=51, vel_seed=52, w_seed=0),
+    "box23k": dict(kind="periodic", n=23000, pos_seed=53, vel_seed=54, w_seed=0),
 }
 
 
@@ -237,6 +270,8 @@ def make_config(name: str, **override) -> System:
     args = dict(CONFIGS[name])
     args.update(override)
     kind = args.pop("kind")
+    if kind == "periodic":
+        return _periodic(name, args["n"], args["pos_seed"], args["vel_seed"], args["w_seed"])
     if kind == "single":
         return _single(name, args["n"], args["pos_seed"], args["vel_seed"], args["w_seed"],
                        cube=args.get("cube"), counts=args.get("counts"))

@@ -408,3 +408,82 @@ def test_langevin_harmonic_configurations_exact(dt):
     wdt = math.sqrt(2.0 * KAPPA) * dt
     assert np.mean(xs) / (KB * T / 2) == pytest.approx(1.0, abs=0.02)
     assert np.mean(ks) / (1.5 * n * KB * T) == pytest.approx(1.0 - wdt ** 2 / 4, abs=0.02)
+
+
+# -------------------------------------------------- periodic boxes (images)
+
+def _supercell(pos, box, axis):
+    shift = np.zeros(3)
+    shift[axis] = box[axis]
+    big = np.array(box, dtype=float)
+    big[axis] *= 2
+    return np.concatenate([pos, pos + shift]), big
+
+
+def test_periodic_large_box_equals_gas_phase(make_system):
+    """A molecule in a box much larger than its extent and the 10.4 A reach
+    (shifted so that wrapping moves atoms across faces) has its gas-phase
+    energy and forces."""
+    s = make_system("mol22")
+    pos = s.pos + np.array([-5.0, 37.0, 100.0])
+    E, Ei, F = oracle.periodic_energy_forces(pos, s.species, s.weights, [60.0, 61.0, 62.0])
+    Eg, Eig, Fg = oracle.energy_forces(s.pos, s.species, s.weights)
+    assert E == pytest.approx(Eg, rel=1e-12)
+    np.testing.assert_allclose(F, Fg, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_periodic_supercell_is_two_copies(make_system, axis):
+    """The box doubled along one axis with the atoms copied is the same
+    crystal: twice the energy, the same forces on both copies.  A missing or
+    doubly counted image breaks this."""
+    s = make_system("box250")
+    E1, Ei1, F1 = oracle.periodic_energy_forces(s.pos, s.species, s.weights, s.box)
+    p2, b2 = _supercell(s.pos, s.box, axis)
+    E2, Ei2, F2 = oracle.periodic_energy_forces(p2, np.concatenate([s.species, s.species]), s.weights, b2)
+    assert E2 == pytest.approx(2 * E1, rel=1e-12)
+    np.testing.assert_allclose(F2[:250], F1, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(F2[250:], F1, rtol=0, atol=1e-10)
+    assert np.abs(F1).max() > 0.1
+
+
+def test_periodic_forces_finite_differences(make_system):
+    """Central differences of the periodic energy (h = 1e-4 A) moving one atom
+    (the images follow through the wrap) equal the analytic forces."""
+    s = make_system("box250")
+    _, _, F = oracle.periodic_energy_forces(s.pos, s.species, s.weights, s.box)
+    h = 1e-4
+    for a in (0, 77, 249):
+        for c in range(3):
+            e = []
+            for sign in (1, -1):
+                p = s.pos.copy()
+                p[a, c] += sign * h
+                e.append(oracle.periodic_energy_forces(p, s.species, s.weights, s.box, forces=False)[0])
+            assert -(e[0] - e[1]) / (2 * h) == pytest.approx(F[a, c], abs=2e-6)
+
+
+def test_periodic_translation_and_net_force(make_system):
+    """Translating every atom (any vector, wrapped or not) changes nothing;
+    the forces sum to zero."""
+    s = make_system("box250")
+    E, Ei, F = oracle.periodic_energy_forces(s.pos, s.species, s.weights, s.box)
+    E2, Ei2, F2 = oracle.periodic_energy_forces(s.pos + np.array([31.7, -5.2, 13.57 * 3 + 0.4]),
+                                               s.species, s.weights, s.box)
+    assert E2 == pytest.approx(E, rel=1e-12)
+    np.testing.assert_allclose(F2, F, rtol=0, atol=1e-10)
+    assert np.abs(F.sum(axis=0)).max() < 1e-9
+
+
+def test_periodic_local_environment_matches_images(make_system):
+    """For a box wider than 20.8 A, the gas-phase force on an atom among the
+    nearest images within 10.4 A (the route the large-system GPU tests take)
+    equals the explicit-image periodic force."""
+    s = synth.make_config("box250", n=1000)
+    assert s.box[0] > 20.8
+    _, _, F = oracle.periodic_energy_forces(s.pos, s.species, s.weights, s.box)
+    for a in (3, 500, 999):
+        idx, x = oracle.periodic_local_environment(s.pos, s.box, a, 10.4)
+        loc = int(np.nonzero(idx == a)[0][0])
+        Fa = oracle.forces_on(x, s.species[idx], s.weights, [loc])[0]
+        np.testing.assert_allclose(Fa, F[a], rtol=0, atol=1e-11)

@@ -79,3 +79,19 @@ def test_golden_mol22_regression():
     x, v, U, K = oracle.vv(s.pos, s.vel, s.masses, s.species, s.weights, 0.5, 100)
     np.testing.assert_allclose(x, np.array(ref["final_positions"]), atol=1e-11)
     np.testing.assert_allclose(U, np.array(ref["U"]), atol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["box250", "box2500"])
+def test_periodic_boxes(name):
+    """Periodic cubes at 0.1 atoms/A^3: positions in [0, L), minimum distance
+    between nearest images >= 0.9 A, the 50:30:10:10 composition, box edge at
+    least twice the pair-list radius 6.2 A."""
+    from scipy.spatial import cKDTree
+    s = synth.make_config(name)
+    L = s.box[0]
+    assert L == pytest.approx((s.n_atoms / 0.1) ** (1 / 3))
+    assert L >= 12.4
+    assert s.pos.min() >= 0.0 and s.pos.max() < L
+    d, _ = cKDTree(s.pos, boxsize=s.box).query(s.pos, k=2)
+    assert d[:, 1].min() >= 0.9
+    assert list(np.bincount(s.species, minlength=4)) == synth.composition_counts(s.n_atoms)
