@@ -189,6 +189,31 @@ def langevin_leg(P, s, dtype, path, steps, warmup):
         ctx.close()
 
 
+def periodic_leg(P, dtype, path, steps, warmup):
+    """A periodic 2,500-atom box (L = 29.24 A, same density): NVE MD steps/s
+    with nearest-image pair lists, and the force error against the oracle's
+    explicit-image periodic forces at the initial configuration."""
+    import oracle
+    import synth
+    s = synth.make_config("box2500")
+    _, _, F_ref = oracle.periodic_energy_forces(s.pos, s.species, s.weights, s.box)
+    ctx = P.Context.from_system(s, dtype=dtype, path=path)
+    try:
+        _, F = ctx.compute(s.pos)
+        ctx.set_state(s.pos, s.vel)
+        ctx.step(DT_FS, warmup, graph=True)
+        ctx.stats()
+        t0 = time.perf_counter()
+        ctx.step(DT_FS, steps, graph=True)
+        st = ctx.stats()
+        t1 = time.perf_counter()
+        return {"workload": "box2500: 2,500 atoms, periodic cube L = %.2f A" % s.box[0], "dtype": dtype,
+                "path": path, "steps_per_s": steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+                "max_force_err": float(np.abs(F - F_ref).max()), "rebuilds": st["rebuilds"]}
+    finally:
+        ctx.close()
+
+
 def batch_leg(P, steps, warmup):
     """256 molecules of 10-300 atoms: molecule-steps/s of one batched context
     (one evaluation launch per step for all molecules, graph-replayed) against
@@ -522,6 +547,9 @@ def main():
     log("langevin")
     out["langevin"] = langevin_leg(P, s, best["dtype"], best["path"], args.steps, args.warmup)
     log("  ", json.dumps(out["langevin"]))
+    log("periodic")
+    out["periodic_box2500"] = periodic_leg(P, best["dtype"], best["path"], args.steps, args.warmup)
+    log("  ", json.dumps(out["periodic_box2500"]))
     if not args.no_batch:
         log("batch256")
         out["batch256"] = batch_leg(P, 100, 20)

@@ -11,7 +11,8 @@
  *                                                           Langevin: nnp_set_thermostat)
  *
  * The model is a symmetry-function network potential:
- *   - pair sets within 5.2 A (radial) and 3.5 A (angular), gas phase (no box);
+ *   - pair sets within 5.2 A (radial) and 3.5 A (angular), gas phase or an
+ *     orthorhombic periodic box (nearest images; nnp_set_box);
  *   - 64 radial features (16 Gaussians, eta = 16 A^-2, centres 0.9..5.1 A, cosine
  *     cutoff 5.2 A, per neighbour element) and 320 angular features (4 shells x 8
  *     sectors, zeta = 32, cosine cutoff 3.5 A, per unordered element pair);
@@ -126,7 +127,9 @@ void nnp_destroy(nnp_context* ctx);
 /* Energy (and forces) at the given positions (the force-provider call).
  *   pos     host [n_atoms][3] double, caller order.  Must be finite, no two
  *           atoms of one molecule closer than 1e-6 A (else NNP_ERR_NONFINITE);
- *   box     must be NULL (gas phase; a periodic box is NNP_ERR_UNSUPPORTED);
+ *   box     NULL keeps the context's box (gas phase unless nnp_set_box gave
+ *           one); else host [3] double, the edges of an orthorhombic periodic
+ *           box, which becomes the context's box as with nnp_set_box;
  *   energy  host [n_molecules] double, molecule potential energies (eV);
  *   forces  host [n_atoms][3] double (eV/A), or NULL for energy only.
  * The positions become the context's current positions (velocities are kept);
@@ -161,6 +164,19 @@ nnp_status nnp_compute_device(nnp_context* ctx, const void* d_pos, int d_pos_is_
  *   preceding nnp_energy_device call. */
 nnp_status nnp_energy_device(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy, int keep);
 nnp_status nnp_forces_device(nnp_context* ctx, double* d_forces);
+
+/* Periodic boundary conditions (the force provider's compute(positions, box)
+ * contract, Methods): box = host [3] double, the edges (A) of an orthorhombic
+ * box with one corner at the origin, or NULL for the gas phase (the default).
+ * Every displacement takes the nearest periodic image; positions are never
+ * wrapped (MD keeps unwrapped coordinates).  Each edge must be finite and at
+ * least 2 (5.2 + skin) A, so that every atom pair within the pair-list radius
+ * has exactly one image in range (else NNP_ERR_ARG); the context must hold
+ * one molecule (else NNP_ERR_UNSUPPORTED).  A molecule of more than 4,096
+ * atoms uses a cell list tiling the box when every edge holds at least three
+ * cells of 5.2 + skin A.  A new box invalidates the pair list and the
+ * captured graphs; the next evaluation rebuilds.  Synchronises. */
+nnp_status nnp_set_box(nnp_context* ctx, const double* box);
 
 /* Sets positions and velocities (host [n_atoms][3] double, caller order;
  * either may be NULL to keep the current value). Forces are recomputed lazily. */

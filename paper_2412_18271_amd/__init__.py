@@ -1,4 +1,5 @@
-"""MI355X-native gas-phase NNP energy/force evaluation and NVE MD.
+"""MI355X-native NNP energy/force evaluation and MD (gas phase or periodic
+boxes; velocity Verlet or Langevin dynamics).
 
 The compute path is the HIP library ``libnnp_hip.so`` behind the C ABI of
 ``include/nnp.h``; this package only marshals arguments to it.  PyTorch is

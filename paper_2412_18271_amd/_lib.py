@@ -23,7 +23,7 @@ EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nn
            "nnp_forces_device", "nnp_set_state",
            "nnp_get_state", "nnp_step", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
            "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels", "nnp_time_steps",
-           "nnp_set_thermostat",
+           "nnp_set_thermostat", "nnp_set_box",
            "nnp_debug_fp8_encode",
            "nnp_last_error", "nnp_status_string")
 
@@ -104,6 +104,7 @@ def load():
         "nnp_time_kernels": (st, [vp, i32, P(d)]),
         "nnp_time_steps": (st, [vp, d, i32, P(d)]),
         "nnp_set_thermostat": (st, [vp, d, d, ctypes.c_uint64]),
+        "nnp_set_box": (st, [vp, P(d)]),
         "nnp_debug_fp8_encode": (st, [P(ctypes.c_float), i32, vp, vp]),
         "nnp_last_error": (ctypes.c_char_p, [vp]),
         "nnp_status_string": (ctypes.c_char_p, [st]),

@@ -67,7 +67,7 @@ class NNPModel(torch.nn.Module):
     """
 
     def __init__(self, species, masses, weights, mol_offsets=None, dtype: str = "bf16x3",
-                 mode: str = "recompute", device: str = "cuda", **kw):
+                 mode: str = "recompute", device: str = "cuda", box=None, **kw):
         super().__init__()
         if mode not in ("recompute", "store"):
             raise ValueError("mode must be 'recompute' or 'store'")
@@ -75,6 +75,8 @@ class NNPModel(torch.nn.Module):
         self.device = torch.device(device)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         self.ctx = Context(species, masses, weights, mol_offsets, dtype=dtype, stream=stream, **kw)
+        if box is not None:
+            self.ctx.set_box(box)
         self.n_molecules = self.ctx.n_molecules
         off = np.asarray(self.ctx._off)
         mol = np.repeat(np.arange(self.n_molecules), np.diff(off))
@@ -84,6 +86,7 @@ class NNPModel(torch.nn.Module):
 
     @classmethod
     def from_system(cls, system, **kw):
+        kw.setdefault("box", getattr(system, "box", None))
         return cls(system.species, system.masses, system.weights, system.mol_offsets, **kw)
 
     def _ensure_layout(self, p):

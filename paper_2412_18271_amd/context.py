@@ -63,7 +63,15 @@ class Context:
 
     @classmethod
     def from_system(cls, system, **kw):
-        return cls(system.species, system.masses, system.weights, system.mol_offsets, **kw)
+        ctx = cls(system.species, system.masses, system.weights, system.mol_offsets, **kw)
+        if getattr(system, "box", None) is not None:
+            ctx.set_box(system.box)
+        return ctx
+
+    def set_box(self, box):
+        """Orthorhombic periodic box edges (3,) in A, or None for the gas phase."""
+        b = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(3)
+        self._check(self._lib.nnp_set_box(self._h, _dptr(b)))
 
     # ------------------------------------------------------------------
     def _check(self, s):

@@ -74,6 +74,9 @@ struct nnp_context {
     int diff_state = 0;         // 0: none, 1: energy evaluated (recompute), 2: energy + kept G, dE/dG
     // captured MD blocks by (steps, dt, path, dtype, tile, friction, kT, seed)
     std::map<std::tuple<int, double, int, int, int, double, double, unsigned long long>, hipGraphExec_t> graphs;
+    // periodic box (edges, A); all zero in the gas phase
+    double box[3] = {0.0, 0.0, 0.0};
+    long long cell_cap = 0;  // cells the cell-list arrays hold
     // pinned staging
     double* h_stage = nullptr;
     size_t h_stage_bytes = 0;
@@ -113,6 +116,16 @@ void* dev_alloc(nnp_context* c, size_t bytes, hipError_t* e)
     return p;
 }
 
+void dev_free(nnp_context* c, const void* p)
+{
+    for (size_t i = 0; i < c->bufs.size(); ++i)
+        if (c->bufs[i].p == p) {
+            (void)hipFree(c->bufs[i].p);
+            c->bufs.erase(c->bufs.begin() + (long)i);
+            return;
+        }
+}
+
 uint32_t spread_bits(uint32_t v)
 {
     v &= 0x3ff;
@@ -129,12 +142,17 @@ nnp_status check_positions(nnp_context* c, const double* pos)
 {
     for (int i = 0; i < 3 * c->n; ++i)
         if (!std::isfinite(pos[i])) return fail(c, NNP_ERR_NONFINITE, "non-finite position component");
+    const bool per = c->S.periodic != 0;
+    auto coord = [&](int i, int d) {
+        const double x = pos[3 * i + d];
+        return per ? x - c->box[d] * std::floor(x / c->box[d]) : x;
+    };
     std::unordered_map<long long, std::vector<int>> grid;
     for (int m = 0; m < c->nmol; ++m) {
         grid.clear();
         for (int i = c->mol_offsets[m]; i < c->mol_offsets[m + 1]; ++i) {
-            const long long gx = (long long)std::floor(pos[3 * i]), gy = (long long)std::floor(pos[3 * i + 1]),
-                            gz = (long long)std::floor(pos[3 * i + 2]);
+            const long long gx = (long long)std::floor(coord(i, 0)), gy = (long long)std::floor(coord(i, 1)),
+                            gz = (long long)std::floor(coord(i, 2));
             for (int dx = -1; dx <= 1; ++dx)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dz = -1; dz <= 1; ++dz) {
@@ -142,8 +160,13 @@ nnp_status check_positions(nnp_context* c, const double* pos)
                         auto it = grid.find(key);
                         if (it == grid.end()) continue;
                         for (int j : it->second) {
-                            const double ex = pos[3 * i] - pos[3 * j], ey = pos[3 * i + 1] - pos[3 * j + 1],
-                                         ez = pos[3 * i + 2] - pos[3 * j + 2];
+                            double ex = pos[3 * i] - pos[3 * j], ey = pos[3 * i + 1] - pos[3 * j + 1],
+                                   ez = pos[3 * i + 2] - pos[3 * j + 2];
+                            if (per) {
+                                ex -= c->box[0] * std::nearbyint(ex / c->box[0]);
+                                ey -= c->box[1] * std::nearbyint(ey / c->box[1]);
+                                ez -= c->box[2] * std::nearbyint(ez / c->box[2]);
+                            }
                             if (ex * ex + ey * ey + ez * ez < 1e-12) {
                                 char b[128];
                                 snprintf(b, sizeof b, "atoms %d and %d coincide", j, i);
@@ -256,6 +279,102 @@ nnp_status rebalance_tiles(nnp_context* c)
     return NNP_OK;
 }
 
+// Cell grids of the molecules with more than kBruteMax atoms (the others scan
+// every atom of their molecule).  Gas phase: a grid around the molecule's
+// positions `pos` (caller order) with margins; periodic box: the box itself
+// split into floor(L / (5.2 + skin)) cells per edge when that is at least 3
+// in every dimension (else the scan with nearest images).
+nnp_status setup_grids(nnp_context* c, const double* pos)
+{
+    Sys& S = c->S;
+    std::vector<int> molgrid(c->nmol, -1);
+    std::vector<CellGrid> grids;
+    long long ncells = 0;
+    const double rl = 5.2 + c->skin;
+    for (int m = 0; m < c->nmol; ++m) {
+        const int lo = c->mol_offsets[m], hi = c->mol_offsets[m + 1];
+        if (hi - lo <= kBruteMax) continue;
+        CellGrid G{};
+        int nd[3];
+        if (S.periodic) {
+            long long cells = 1;
+            for (int d = 0; d < 3; ++d) {
+                nd[d] = (int)std::min<double>(std::floor(c->box[d] / rl), 1024.0);
+                cells *= nd[d];
+            }
+            if (nd[0] < 3 || nd[1] < 3 || nd[2] < 3) continue;
+            while (cells > kMaxCellsPerGrid) {
+                cells = 1;
+                for (int d = 0; d < 3; ++d) {
+                    nd[d] = std::max(3, (nd[d] * 4) / 5);
+                    cells *= nd[d];
+                }
+            }
+            G.ox = G.oy = G.oz = 0.0;
+            G.ihx = nd[0] / c->box[0];
+            G.ihy = nd[1] / c->box[1];
+            G.ihz = nd[2] / c->box[2];
+            G.periodic = 1;
+        } else {
+            double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+            for (int i = lo; i < hi; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    mn[d] = std::min(mn[d], pos[3 * i + d]);
+                    mx[d] = std::max(mx[d], pos[3 * i + d]);
+                }
+            double org[3], span[3];
+            for (int d = 0; d < 3; ++d) {
+                const double L = mx[d] - mn[d];
+                const double margin = std::max(2.0 * rl, 0.5 * L);
+                org[d] = mn[d] - margin;
+                span[d] = L + 2.0 * margin;
+            }
+            double h = rl;
+            for (;;) {
+                long long cells = 1;
+                for (int d = 0; d < 3; ++d) {
+                    nd[d] = std::max(1, (int)std::ceil(span[d] / h));
+                    cells *= nd[d];
+                }
+                if (cells <= kMaxCellsPerGrid) break;
+                h *= 1.25;
+            }
+            G.ox = org[0];
+            G.oy = org[1];
+            G.oz = org[2];
+            G.ihx = G.ihy = G.ihz = 1.0 / h;
+            G.periodic = 0;
+        }
+        G.nx = nd[0];
+        G.ny = nd[1];
+        G.nz = nd[2];
+        G.first = (int)ncells;
+        ncells += (long long)nd[0] * nd[1] * nd[2];
+        molgrid[m] = (int)grids.size();
+        grids.push_back(G);
+    }
+    HIP_TRY(c, hipMemcpy((void*)S.molgrid, molgrid.data(), sizeof(int) * c->nmol, hipMemcpyHostToDevice));
+    if (ncells > c->cell_cap) {
+        dev_free(c, S.grids);
+        dev_free(c, S.cell_count);
+        dev_free(c, S.cell_start);
+        dev_free(c, S.cell_fill);
+        hipError_t e = hipSuccess;
+        S.grids = (const CellGrid*)dev_alloc(c, sizeof(CellGrid) * c->nmol, &e);
+        if (e == hipSuccess) S.cell_count = (int*)dev_alloc(c, sizeof(int) * ncells, &e);
+        if (e == hipSuccess) S.cell_start = (int*)dev_alloc(c, sizeof(int) * (ncells + 1), &e);
+        if (e == hipSuccess) S.cell_fill = (int*)dev_alloc(c, sizeof(int) * ncells, &e);
+        if (e == hipSuccess && !S.cell_atoms) S.cell_atoms = (int*)dev_alloc(c, sizeof(int) * c->n, &e);
+        if (e == hipSuccess && !S.cellof) S.cellof = (int*)dev_alloc(c, sizeof(int) * c->n, &e);
+        if (e != hipSuccess) return hip_fail(c, e, "cell list allocation");
+        c->cell_cap = ncells;
+    }
+    S.ncells = (int)ncells;
+    if (ncells > 0)
+        HIP_TRY(c, hipMemcpy((void*)S.grids, grids.data(), sizeof(CellGrid) * grids.size(), hipMemcpyHostToDevice));
+    return NNP_OK;
+}
+
 // Builds the internal order from the first positions and uploads every
 // per-atom constant.
 nnp_status lay_out(nnp_context* c, const double* pos)
@@ -265,16 +384,20 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     for (int m = 0; m < c->nmol; ++m) {
         const int lo = c->mol_offsets[m], hi = c->mol_offsets[m + 1];
         double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        auto coord = [&](int i, int d) {
+            const double x = pos[3 * i + d];
+            return c->S.periodic ? x - c->box[d] * std::floor(x / c->box[d]) : x;
+        };
         for (int i = lo; i < hi; ++i)
             for (int d = 0; d < 3; ++d) {
-                mn[d] = std::min(mn[d], pos[3 * i + d]);
-                mx[d] = std::max(mx[d], pos[3 * i + d]);
+                mn[d] = std::min(mn[d], coord(i, d));
+                mx[d] = std::max(mx[d], coord(i, d));
             }
         for (int i = lo; i < hi; ++i) {
             uint32_t q[3];
             for (int d = 0; d < 3; ++d) {
                 const double span = std::max(mx[d] - mn[d], 1e-9);
-                q[d] = (uint32_t)std::min(1023.0, std::floor((pos[3 * i + d] - mn[d]) / span * 1023.999));
+                q[d] = (uint32_t)std::min(1023.0, std::max(0.0, std::floor((coord(i, d) - mn[d]) / span * 1023.999)));
             }
             const uint64_t morton = spread_bits(q[0]) | (spread_bits(q[1]) << 1) | (spread_bits(q[2]) << 2);
             key[i] = ((uint64_t)c->species[i] << 60) | ((uint64_t)m << 32) | morton;
@@ -319,63 +442,9 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     std::vector<int> perm_dev(c->perm.begin(), c->perm.end());
     Sys& S = c->S;
     S.ntiles = (int)tiles.size();
-    // cell grids of large molecules, fixed from the first positions
-    std::vector<int> molgrid(c->nmol, -1);
-    std::vector<CellGrid> grids;
-    long long ncells = 0;
-    const double rl = 5.2 + c->skin;
-    for (int m = 0; m < c->nmol; ++m) {
-        const int lo = c->mol_offsets[m], hi = c->mol_offsets[m + 1];
-        if (hi - lo <= kBruteMax) continue;
-        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-        for (int i = lo; i < hi; ++i)
-            for (int d = 0; d < 3; ++d) {
-                mn[d] = std::min(mn[d], pos[3 * i + d]);
-                mx[d] = std::max(mx[d], pos[3 * i + d]);
-            }
-        double org[3], span[3];
-        for (int d = 0; d < 3; ++d) {
-            const double L = mx[d] - mn[d];
-            const double margin = std::max(2.0 * rl, 0.5 * L);
-            org[d] = mn[d] - margin;
-            span[d] = L + 2.0 * margin;
-        }
-        double h = rl;
-        int nd[3];
-        for (;;) {
-            long long cells = 1;
-            for (int d = 0; d < 3; ++d) {
-                nd[d] = std::max(1, (int)std::ceil(span[d] / h));
-                cells *= nd[d];
-            }
-            if (cells <= kMaxCellsPerGrid) break;
-            h *= 1.25;
-        }
-        CellGrid G;
-        G.ox = org[0];
-        G.oy = org[1];
-        G.oz = org[2];
-        G.inv_h = 1.0 / h;
-        G.nx = nd[0];
-        G.ny = nd[1];
-        G.nz = nd[2];
-        G.first = (int)ncells;
-        ncells += (long long)nd[0] * nd[1] * nd[2];
-        molgrid[m] = (int)grids.size();
-        grids.push_back(G);
-    }
-    HIP_TRY(c, hipMemcpy((void*)S.molgrid, molgrid.data(), sizeof(int) * c->nmol, hipMemcpyHostToDevice));
-    S.ncells = (int)ncells;
-    if (ncells > 0) {
-        hipError_t e = hipSuccess;
-        S.grids = (const CellGrid*)dev_alloc(c, sizeof(CellGrid) * grids.size(), &e);
-        if (e == hipSuccess) S.cell_count = (int*)dev_alloc(c, sizeof(int) * ncells, &e);
-        if (e == hipSuccess) S.cell_start = (int*)dev_alloc(c, sizeof(int) * (ncells + 1), &e);
-        if (e == hipSuccess) S.cell_fill = (int*)dev_alloc(c, sizeof(int) * ncells, &e);
-        if (e == hipSuccess) S.cell_atoms = (int*)dev_alloc(c, sizeof(int) * n, &e);
-        if (e == hipSuccess) S.cellof = (int*)dev_alloc(c, sizeof(int) * n, &e);
-        if (e != hipSuccess) return hip_fail(c, e, "cell list allocation");
-        HIP_TRY(c, hipMemcpy((void*)S.grids, grids.data(), sizeof(CellGrid) * grids.size(), hipMemcpyHostToDevice));
+    {
+        const nnp_status gs = setup_grids(c, pos);
+        if (gs != NNP_OK) return gs;
     }
     HIP_TRY(c, hipMemcpy(S.pos, p4.data(), sizeof(double4) * n, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy((void*)S.kinv, kinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
@@ -867,11 +936,63 @@ nnp_status nnp_set_state(nnp_context* c, const double* pos, const double* vel)
     return NNP_OK;
 }
 
+nnp_status nnp_set_box(nnp_context* c, const double* box)
+{
+    if (!c) return NNP_ERR_ARG;
+    const double rl = 5.2 + c->skin;
+    if (box) {
+        if (c->nmol != 1) return fail(c, NNP_ERR_UNSUPPORTED, "a periodic box needs n_molecules == 1");
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(box[d]) || !(box[d] >= 2.0 * rl)) {
+                char b[160];
+                snprintf(b, sizeof b, "box edges must be finite and >= 2 (5.2 + skin) = %.2f A", 2.0 * rl);
+                return fail(c, NNP_ERR_ARG, b);
+            }
+    }
+    const bool same = box ? (c->S.periodic && box[0] == c->box[0] && box[1] == c->box[1] && box[2] == c->box[2])
+                          : !c->S.periodic;
+    if (same) return NNP_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<double> pos;
+    if (c->laid_out && !box) {
+        // back to the gas phase: grids follow the current positions
+        std::vector<double4> p4(c->n);
+        HIP_TRY(c, hipMemcpy(p4.data(), c->S.pos, sizeof(double4) * c->n, hipMemcpyDeviceToHost));
+        pos.resize(3 * (size_t)c->n);
+        for (int k = 0; k < c->n; ++k) {
+            const int i = c->perm[k];
+            pos[3 * i] = p4[k].x;
+            pos[3 * i + 1] = p4[k].y;
+            pos[3 * i + 2] = p4[k].z;
+        }
+    }
+    c->S.periodic = box ? 1 : 0;
+    for (int d = 0; d < 3; ++d) c->box[d] = box ? box[d] : 0.0;
+    c->S.box = make_double3(c->box[0], c->box[1], c->box[2]);
+    c->S.ibox = box ? make_double3(1.0 / box[0], 1.0 / box[1], 1.0 / box[2]) : make_double3(0.0, 0.0, 0.0);
+    if (c->laid_out) {
+        const nnp_status gs = setup_grids(c, pos.empty() ? nullptr : pos.data());
+        if (gs != NNP_OK) return gs;
+        HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->forces_current = false;
+        c->kick_pending = false;
+    }
+    // captured graphs hold the old box in their kernel arguments
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    c->err.clear();
+    return NNP_OK;
+}
+
 nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, double* energy, double* forces)
 {
     if (!c) return NNP_ERR_ARG;
     c->diff_state = 0;
-    if (box) return fail(c, NNP_ERR_UNSUPPORTED, "periodic boxes are not supported (gas phase only)");
+    if (box) {
+        const nnp_status bs = nnp_set_box(c, box);
+        if (bs != NNP_OK) return bs;
+    }
     if (!pos || !energy) return fail(c, NNP_ERR_ARG, "pos and energy are required");
     nnp_status s = upload_positions(c, pos);
     if (s != NNP_OK) return s;

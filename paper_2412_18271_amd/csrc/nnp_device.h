@@ -152,7 +152,8 @@ __device__ __forceinline__ void build_list(const Sys& S, int a)
                 const int c = c0 + 64 * u + lane;
                 bool ok = false;
                 if (c < rg.y && c != a) {
-                    const double dx = pc[u].x - pa.x, dy = pc[u].y - pa.y, dz = pc[u].z - pa.z;
+                    double dx = pc[u].x - pa.x, dy = pc[u].y - pa.y, dz = pc[u].z - pa.z;
+                    min_image(S, dx, dy, dz);
                     ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
                 }
                 const unsigned long long mk = __ballot(ok);
@@ -189,6 +190,7 @@ __device__ __forceinline__ void load_env(const Sys& S, int a, Env& E)
             dx = pj.x - pa.x;
             dy = pj.y - pa.y;
             dz = pj.z - pa.z;
+            min_image(S, dx, dy, dz);
             elem = (int)pj.w;
         }
         env_append(E, valid, s, j, dx, dy, dz, elem, nR, nA, nAs, over);

@@ -94,12 +94,14 @@ struct StepState {
 
 // Cell grid of one large molecule (cells of edge >= 5.2 + skin; atoms outside
 // the grid are clamped into its boundary cells, which keeps every pair within
-// the list cutoff in adjacent cells).
+// the list cutoff in adjacent cells), or of the periodic box (cells tile the
+// box; an atom's cell is that of its position wrapped into the box).
 struct CellGrid {
-    double ox, oy, oz;  // origin
-    double inv_h;       // 1 / cell edge
-    int nx, ny, nz;     // cells per dimension
-    int first;          // index of the grid's first cell in the global cell arrays
+    double ox, oy, oz;     // origin
+    double ihx, ihy, ihz;  // 1 / cell edge per dimension
+    int nx, ny, nz;        // cells per dimension (>= 3 each when periodic)
+    int first;             // index of the grid's first cell in the global cell arrays
+    int periodic;          // cells cover the periodic box and wrap around
 };
 
 struct Sys {
@@ -112,6 +114,10 @@ struct Sys {
     double4* vel;
     double4* frc;
     float4* ref;
+    // orthorhombic periodic box (one molecule); displacements take the nearest
+    // image, positions are never wrapped
+    int periodic;
+    double3 box, ibox;  // edges (A) and their inverses
     // Langevin dynamics (BAOAB) of nnp_step; gamma == 0 selects velocity Verlet
     double gamma;        // friction (1/fs)
     double kT;           // thermostat temperature (eV)
@@ -152,6 +158,17 @@ struct Sys {
     int* cell_atoms;         // [n]
     int* cellof;             // [n]
 };
+
+// Nearest periodic image of a displacement (no-op in the gas phase).  Box
+// edges are at least twice the pair-list radius, so the image is unique.
+__device__ __forceinline__ void min_image(const Sys& S, double& dx, double& dy, double& dz)
+{
+    if (S.periodic) {
+        dx -= S.box.x * rint(dx * S.ibox.x);
+        dy -= S.box.y * rint(dy * S.ibox.y);
+        dz -= S.box.z * rint(dz * S.ibox.z);
+    }
+}
 
 // True when the evaluation that reads this state has to rebuild the pair list.
 __device__ __forceinline__ bool rebuild_due(const StepState* st, int rebuild_every)

@@ -558,9 +558,10 @@ __global__ void k_invalidate_lists(Sys S)
 // scans the 27 cells around it and keeps the neighbours within 5.2 + skin,
 // sorted ascending (the order every consumer of the pair list relies on).
 
-__device__ __forceinline__ int clamp_cell(double x, double o, double inv_h, int n)
+__device__ __forceinline__ int cell_coord(double x, double o, double inv_h, int n, int periodic)
 {
-    const double f = floor((x - o) * inv_h);
+    double f = floor((x - o) * inv_h);
+    if (periodic) f -= (double)n * floor(f / (double)n);  // f mod n
     return f < 0.0 ? 0 : (f >= (double)n ? n - 1 : (int)f);
 }
 
@@ -585,8 +586,10 @@ __global__ __launch_bounds__(256) void k_cell_count(Sys S)
     }
     const CellGrid G = S.grids[g];
     const double4 p = S.pos[a];
-    const int c = G.first + (clamp_cell(p.z, G.oz, G.inv_h, G.nz) * G.ny + clamp_cell(p.y, G.oy, G.inv_h, G.ny)) * G.nx +
-                  clamp_cell(p.x, G.ox, G.inv_h, G.nx);
+    const int c = G.first +
+                  (cell_coord(p.z, G.oz, G.ihz, G.nz, G.periodic) * G.ny + cell_coord(p.y, G.oy, G.ihy, G.ny, G.periodic)) *
+                      G.nx +
+                  cell_coord(p.x, G.ox, G.ihx, G.nx, G.periodic);
     S.cellof[a] = c;
     atomicAdd(&S.cell_count[c], 1);
 }
@@ -662,17 +665,21 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
     int* K = keys[wave];
     const CellGrid G = S.grids[g];
     const double4 pa = S.pos[a];
-    const int cx = clamp_cell(pa.x, G.ox, G.inv_h, G.nx), cy = clamp_cell(pa.y, G.oy, G.inv_h, G.ny),
-              cz = clamp_cell(pa.z, G.oz, G.inv_h, G.nz);
+    const int cx = cell_coord(pa.x, G.ox, G.ihx, G.nx, G.periodic), cy = cell_coord(pa.y, G.oy, G.ihy, G.ny, G.periodic),
+              cz = cell_coord(pa.z, G.oz, G.ihz, G.nz, G.periodic);
     int count = 0;
+    // periodic grids have >= 3 cells per dimension, so the 27 wrapped cells are distinct
     for (int dz = -1; dz <= 1; ++dz) {
-        const int z = cz + dz;
+        int z = cz + dz;
+        if (G.periodic) z = z < 0 ? z + G.nz : (z >= G.nz ? z - G.nz : z);
         if (z < 0 || z >= G.nz) continue;
         for (int dy = -1; dy <= 1; ++dy) {
-            const int y = cy + dy;
+            int y = cy + dy;
+            if (G.periodic) y = y < 0 ? y + G.ny : (y >= G.ny ? y - G.ny : y);
             if (y < 0 || y >= G.ny) continue;
             for (int dx = -1; dx <= 1; ++dx) {
-                const int x = cx + dx;
+                int x = cx + dx;
+                if (G.periodic) x = x < 0 ? x + G.nx : (x >= G.nx ? x - G.nx : x);
                 if (x < 0 || x >= G.nx) continue;
                 const int c = G.first + (z * G.ny + y) * G.nx + x;
                 const int b0 = S.cell_start[c], b1 = S.cell_start[c + 1];
@@ -684,7 +691,8 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
                         b = S.cell_atoms[i];
                         if (b != a) {
                             const double4 pb = S.pos[b];
-                            const double ex = pb.x - pa.x, ey = pb.y - pa.y, ez = pb.z - pa.z;
+                            double ex = pb.x - pa.x, ey = pb.y - pa.y, ez = pb.z - pa.z;
+                            min_image(S, ex, ey, ez);
                             ok = ex * ex + ey * ey + ez * ez < (double)S.rlist2;
                         }
                     }
