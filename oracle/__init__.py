@@ -156,7 +156,8 @@ def forces_on(pos, species, weights, sel) -> np.ndarray:
 
 
 def vv(pos, vel, masses, species, weights, dt: float, nsteps: int, model: int = 0):
-    """NVE velocity Verlet.  Returns (x, v, U[nsteps+1], K[nsteps+1])."""
+    """NVE velocity Verlet.  model 0 = network, 1 = harmonic sum(x^2), 2 = no
+    force, 3 = network plus harmonic.  Returns (x, v, U[nsteps+1], K[nsteps+1])."""
     lib = _load()
     x = _pos(pos).copy()
     v = _pos(vel).copy()

@@ -446,15 +446,34 @@ static double kinetic(int n, const double* v, const double* m)
     return K;
 }
 
+/* Force model of the integrators: 0 network, 1 harmonic sum(x^2), 2 none,
+ * 3 network plus harmonic (two force providers whose energies and forces add). */
+static double model_forces(int model, int n, const double* x, const int* sp, const float* weights, double* F)
+{
+    if (model == 1) return harmonic(n, x, F);
+    if (model == 2) {
+        memset(F, 0, sizeof(double) * 3 * (size_t)n);
+        return 0.0;
+    }
+    double E = oracle_energy_forces(n, x, sp, weights, NULL, F);
+    if (model == 3) {
+        double* Fh = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        E += harmonic(n, x, Fh);
+        for (int i = 0; i < 3 * n; ++i) F[i] += Fh[i];
+        free(Fh);
+    }
+    return E;
+}
+
 /* O8: nsteps of NVE velocity Verlet on one molecule, in place on x and v
- * (both [n][3]).  model 0 = network potential, 1 = harmonic sum(x^2).
+ * (both [n][3]).  model: see model_forces.
  * U[nsteps+1] and K[nsteps+1] (optional) receive the potential and kinetic
  * energy before the first step and after every step. */
 void oracle_vv(int n, double* x, double* v, const double* m, const int* sp, const float* weights, int model,
                double dt, int nsteps, double* U, double* K)
 {
     double* F = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-    double E = model == 1 ? harmonic(n, x, F) : oracle_energy_forces(n, x, sp, weights, NULL, F);
+    double E = model_forces(model, n, x, sp, weights, F);
     if (U) U[0] = E;
     if (K) K[0] = kinetic(n, v, m);
     for (int s = 1; s <= nsteps; ++s) {
@@ -463,24 +482,13 @@ void oracle_vv(int n, double* x, double* v, const double* m, const int* sp, cons
                 v[3 * i + c] += 0.5 * dt * KAPPA * F[3 * i + c] / m[i];
                 x[3 * i + c] += dt * v[3 * i + c];
             }
-        E = model == 1 ? harmonic(n, x, F) : oracle_energy_forces(n, x, sp, weights, NULL, F);
+        E = model_forces(model, n, x, sp, weights, F);
         for (int i = 0; i < n; ++i)
             for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * KAPPA * F[3 * i + c] / m[i];
         if (U) U[s] = E;
         if (K) K[s] = kinetic(n, v, m);
     }
     free(F);
-}
-
-/* Force model of the integrators: 0 network, 1 harmonic sum(x^2), 2 none. */
-static double model_forces(int model, int n, const double* x, const int* sp, const float* weights, double* F)
-{
-    if (model == 1) return harmonic(n, x, F);
-    if (model == 2) {
-        memset(F, 0, sizeof(double) * 3 * (size_t)n);
-        return 0.0;
-    }
-    return oracle_energy_forces(n, x, sp, weights, NULL, F);
 }
 
 /* O10: Philox4x64-10.  Each of the ten rounds multiplies counter words 0 and

@@ -487,3 +487,19 @@ def test_periodic_local_environment_matches_images(make_system):
         loc = int(np.nonzero(idx == a)[0][0])
         Fa = oracle.forces_on(x, s.species[idx], s.weights, [loc])[0]
         np.testing.assert_allclose(Fa, F[a], rtol=0, atol=1e-11)
+
+
+def test_two_force_providers_add(make_system):
+    """Model 3 (network plus the harmonic sum x^2 as a second force provider):
+    the starting energy is the sum of the two providers' energies, and the
+    combined NVE dynamics conserves H to second order in dt."""
+    s = make_system("mol22")
+    x = s.pos - s.pos.mean(axis=0)
+    _, _, U, K = oracle.vv(x, s.vel, s.masses, s.species, s.weights, 0.5, 0, model=3)
+    E = oracle.energy_forces(x, s.species, s.weights, forces=False)[0]
+    assert U[0] == pytest.approx(E + (x ** 2).sum(), rel=1e-14)
+    amp = []
+    for dt, steps in ((0.5, 100), (0.25, 200)):
+        _, _, U, K = oracle.vv(x, s.vel, s.masses, s.species, s.weights, dt, steps, model=3)
+        amp.append(np.max(np.abs(U + K - U[0] - K[0])))
+    assert 3.0 < amp[0] / amp[1] < 5.0
