@@ -199,6 +199,34 @@ nnp_status nnp_get_state(nnp_context* ctx, double* pos, double* vel, double* for
  * nnp_get_state / nnp_energy_log synchronise. */
 nnp_status nnp_step(nnp_context* ctx, double dt_fs, int32_t n_steps, int32_t use_graph);
 
+/* Extra force providers (the paper's callback mechanism, Methods: the engine
+ * calls back into caller code for energies and forces; its explicit-force
+ * provider, AIMD section): after every network evaluation of nnp_compute,
+ * nnp_compute_device (with forces) and nnp_step, each registered provider is
+ * called on the host thread of that call as
+ *   rc = fn(user, n_atoms, n_molecules, d_pos, d_forces, d_energy, stream)
+ * with d_pos holding the current positions (caller order, [n_atoms][3]
+ * double, A) and d_forces ([n_atoms][3] double) and d_energy ([n_molecules]
+ * double) cleared; it enqueues work on `stream` (the context stream, a
+ * hipStream_t) or works synchronously, leaving its forces (eV/A) and
+ * per-molecule energies (eV) in those buffers, and returns 0 (anything else:
+ * the calling function returns NNP_ERR_STATE; the evaluation is discarded,
+ * and inside nnp_step the interrupted step leaves positions and velocities
+ * mid-step: set the state again before stepping on).  The library adds them to the
+ * network's forces (64-bit fixed point, 2^-32 eV/A, |component| < 2^30) and
+ * molecule energies (not to the per-atom energies).  The three buffers are
+ * caller-owned device memory and, like `user`, must stay valid until
+ * nnp_clear_forces or nnp_destroy (the paper's keep-alive rule for the
+ * registered model).  With providers registered nnp_step launches its kernels
+ * step by step without graphs, and nnp_time_steps returns NNP_ERR_UNSUPPORTED.
+ * At most 8 providers; NULL fn or buffers: NNP_ERR_ARG. */
+typedef int (*nnp_force_fn)(void* user, int32_t n_atoms, int32_t n_molecules, const double* d_pos,
+                            double* d_forces, double* d_energy, void* stream);
+nnp_status nnp_add_force(nnp_context* ctx, nnp_force_fn fn, void* user, double* d_pos, double* d_forces,
+                         double* d_energy);
+/* Removes every extra force provider (synchronises the context stream). */
+nnp_status nnp_clear_forces(nnp_context* ctx);
+
 /* Thermostat of nnp_step (the paper times its runs with Langevin dynamics at
  * a friction of 0.1 ps^-1, Results section).  friction_per_ps > 0 makes every
  * following step a BAOAB Langevin step (Leimkuhler and Matthews 2013):

@@ -23,9 +23,14 @@ EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nn
            "nnp_forces_device", "nnp_set_state",
            "nnp_get_state", "nnp_step", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
            "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels", "nnp_time_steps",
-           "nnp_set_thermostat", "nnp_set_box",
+           "nnp_set_thermostat", "nnp_set_box", "nnp_add_force", "nnp_clear_forces",
            "nnp_debug_fp8_encode",
            "nnp_last_error", "nnp_status_string")
+
+
+#: nnp_force_fn: (user, n_atoms, n_molecules, d_pos, d_forces, d_energy, stream) -> int
+FORCE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Params(ctypes.Structure):
@@ -105,6 +110,8 @@ def load():
         "nnp_time_steps": (st, [vp, d, i32, P(d)]),
         "nnp_set_thermostat": (st, [vp, d, d, ctypes.c_uint64]),
         "nnp_set_box": (st, [vp, P(d)]),
+        "nnp_add_force": (st, [vp, FORCE_FN, vp, vp, vp, vp]),
+        "nnp_clear_forces": (st, [vp]),
         "nnp_debug_fp8_encode": (st, [P(ctypes.c_float), i32, vp, vp]),
         "nnp_last_error": (ctypes.c_char_p, [vp]),
         "nnp_status_string": (ctypes.c_char_p, [st]),

@@ -77,7 +77,8 @@ class Context:
     def _check(self, s):
         if s != _lib.NNP_OK:
             msg = self._lib.nnp_last_error(self._h)
-            raise NNPError(s, msg.decode() if msg else "")
+            err, self._provider_error = getattr(self, "_provider_error", None), None
+            raise NNPError(s, msg.decode() if msg else "") from err
 
     def close(self):
         if getattr(self, "_h", None):
@@ -140,6 +141,68 @@ class Context:
 
     def step(self, dt: float, n_steps: int, graph: bool = True):
         self._check(self._lib.nnp_step(self._h, float(dt), int(n_steps), 1 if graph else 0))
+
+    def add_force(self, fn, kind: str = "energy"):
+        """Registers an extra force provider summed with the network (the
+        paper's callback mechanism).  ``fn`` is called after every network
+        evaluation with the positions, on the context's stream:
+
+          kind="energy": fn(pos) -> energy; pos is a float64 CUDA tensor
+              [n_atoms, 3] that requires grad, the energy a tensor of one or
+              n_molecules elements; forces are minus its gradient (autograd);
+          kind="forces": fn(pos) -> (energy, forces) as CUDA tensors;
+          kind="numpy":  fn(pos) -> (energy, forces) with pos and the
+              results as NumPy arrays (explicit forces, host code).
+        """
+        import contextlib
+        import torch
+        if kind not in ("energy", "forces", "numpy"):
+            raise ValueError("kind must be 'energy', 'forces' or 'numpy'")
+        n, m = self.n_atoms, self.n_molecules
+        dev = torch.device("cuda", torch.cuda.current_device())
+        pos_t = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        f_t = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        e_t = torch.zeros(m, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize(dev)
+
+        def energies(E):
+            E = torch.as_tensor(E, dtype=torch.float64, device=dev).reshape(-1)
+            if E.numel() not in (1, m):
+                raise ValueError("energy must have 1 or n_molecules elements")
+            return E
+
+        def call(user, n_atoms, n_mol, d_pos, d_f, d_e, stream):
+            try:
+                ctx = (torch.cuda.stream(torch.cuda.ExternalStream(stream, device=dev)) if stream
+                       else contextlib.nullcontext())
+                with ctx:
+                    if kind == "energy":
+                        with torch.enable_grad():
+                            x = pos_t.detach().clone().requires_grad_(True)
+                            E = energies(fn(x))
+                            (g,) = torch.autograd.grad(E.sum(), x)
+                        F = -g
+                    elif kind == "forces":
+                        E, F = fn(pos_t.detach().clone())
+                        E = energies(E)
+                    else:
+                        E, F = fn(pos_t.cpu().numpy())
+                        E = energies(np.asarray(E, dtype=np.float64))
+                    f_t.copy_(torch.as_tensor(F, dtype=torch.float64, device=dev).reshape(n, 3))
+                    e_t.copy_(E.detach().expand(m) if E.numel() == 1 else E.detach())
+                return 0
+            except Exception as exc:  # reported by the calling entry point
+                self._provider_error = exc
+                return 1
+
+        cb = _lib.FORCE_FN(call)
+        self._providers = getattr(self, "_providers", []) + [(cb, pos_t, f_t, e_t)]  # keep alive
+        self._check(self._lib.nnp_add_force(self._h, cb, None, ctypes.c_void_p(pos_t.data_ptr()),
+                                            ctypes.c_void_p(f_t.data_ptr()), ctypes.c_void_p(e_t.data_ptr())))
+
+    def clear_forces(self):
+        self._check(self._lib.nnp_clear_forces(self._h))
+        self._providers = []
 
     def set_thermostat(self, temperature: float = 300.0, friction: float = 0.1, seed: int = 0):
         """Langevin dynamics (BAOAB) for the following steps: temperature in K,

@@ -74,6 +74,15 @@ struct nnp_context {
     int diff_state = 0;         // 0: none, 1: energy evaluated (recompute), 2: energy + kept G, dE/dG
     // captured MD blocks by (steps, dt, path, dtype, tile, friction, kT, seed)
     std::map<std::tuple<int, double, int, int, int, double, double, unsigned long long>, hipGraphExec_t> graphs;
+    // extra force providers (caller callbacks and their device buffers)
+    struct Extra {
+        nnp_force_fn fn;
+        void* user;
+        double* pos;
+        double* frc;
+        double* en;
+    };
+    std::vector<Extra> extra;
     // periodic box (edges, A); all zero in the gas phase
     double box[3] = {0.0, 0.0, 0.0};
     long long cell_cap = 0;  // cells the cell-list arrays hold
@@ -630,6 +639,55 @@ hipError_t enqueue_compute(nnp_context* c, bool grad)
     return launch_gather_integrate(c->S, 0.0, 0, c->stream);
 }
 
+// Runs the extra force providers on the evaluation just enqueued: each gets
+// the positions, adds its forces and energies, and the library adds them to
+// the evaluation's sums before the gather.
+nnp_status apply_extra(nnp_context* c)
+{
+    for (size_t k = 0; k < c->extra.size(); ++k) {
+        const auto& x = c->extra[k];
+        HIP_TRY(c, launch_extra_prepare(c->S, x.pos, x.frc, x.en, c->stream));
+        const int rc = x.fn(x.user, c->n, c->nmol, x.pos, x.frc, x.en, (void*)c->stream);
+        if (rc != 0) {
+            // the evaluation is discarded: a gather without integration empties
+            // its force and energy sums so that the next evaluation starts clean
+            (void)launch_gather_integrate(c->S, 0.0, 0, c->stream);
+            (void)hipStreamSynchronize(c->stream);
+            c->forces_current = false;
+            c->kick_pending = false;
+            char b[96];
+            snprintf(b, sizeof b, "force provider %d returned %d", (int)k, rc);
+            return fail(c, NNP_ERR_STATE, b);
+        }
+        HIP_TRY(c, launch_extra_add(c->S, x.frc, x.en, c->stream));
+    }
+    return NNP_OK;
+}
+
+// One complete evaluation: network forces, extra providers, force gather.
+nnp_status full_compute(nnp_context* c)
+{
+    HIP_TRY(c, enqueue_eval(c, true));
+    const nnp_status xs = apply_extra(c);
+    if (xs != NNP_OK) return xs;
+    HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+    return NNP_OK;
+}
+
+// Steps with extra providers: launched one by one (the providers are host
+// code, so the steps are not captured in graphs).
+nnp_status steps_with_extra(nnp_context* c, double dt, int nsteps)
+{
+    HIP_TRY(c, launch_kickdrift(c->S, dt, c->stream));
+    for (int i = 0; i < nsteps; ++i) {
+        HIP_TRY(c, enqueue_eval(c, true));
+        const nnp_status xs = apply_extra(c);
+        if (xs != NNP_OK) return xs;
+        HIP_TRY(c, launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream));
+    }
+    return NNP_OK;
+}
+
 hipError_t enqueue_steps(nnp_context* c, double dt, int nsteps, bool first_kick)
 {
     hipError_t e = hipSuccess;
@@ -997,7 +1055,8 @@ nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, dou
     nnp_status s = upload_positions(c, pos);
     if (s != NNP_OK) return s;
     HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
-    HIP_TRY(c, enqueue_compute(c, true));
+    s = full_compute(c);
+    if (s != NNP_OK) return s;
     std::vector<double4> f4;
     if (forces) {
         f4.resize(c->n);
@@ -1028,11 +1087,12 @@ nnp_status nnp_compute_device(nnp_context* c, const void* d_pos, int is_f64, dou
     HIP_TRY(c, launch_positions_in(c->S, d_pos, is_f64 ? 1 : 0, c->stream));
     HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
     const bool grad = d_forces != nullptr;
-    HIP_TRY(c, enqueue_eval(c, grad));
     if (grad) {
-        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+        const nnp_status fs = full_compute(c);
+        if (fs != NNP_OK) return fs;
         HIP_TRY(c, launch_forces_out(c->S, d_forces, c->stream));
     } else {
+        HIP_TRY(c, enqueue_eval(c, false));
         HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
     }
     HIP_TRY(c, launch_energy_out(c->S, d_energy, c->stream));
@@ -1050,10 +1110,20 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
     if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before stepping");
     if (nsteps == 0) return NNP_OK;
     if (!c->forces_current) {
-        HIP_TRY(c, enqueue_compute(c, true));
+        const nnp_status fs = full_compute(c);
+        if (fs != NNP_OK) return fs;
         c->forces_current = true;
     }
     const int B = std::min<int>(nsteps, 100);
+    if (!c->extra.empty()) {
+        for (int left = nsteps; left > 0; left -= B) {
+            nnp_status bs = rebalance_tiles(c);
+            if (bs == NNP_OK) bs = steps_with_extra(c, dt, std::min(left, B));
+            if (bs != NNP_OK) return bs;
+        }
+        c->kick_pending = true;
+        return NNP_OK;
+    }
     if (!use_graph || c->stream == nullptr) {
         // blocks of at most 100 steps, as with graphs (tile balancing between
         // blocks gives graph and eager runs the same trajectory)
@@ -1094,6 +1164,27 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         left -= len;
     }
     c->kick_pending = true;
+    return NNP_OK;
+}
+
+nnp_status nnp_add_force(nnp_context* c, nnp_force_fn fn, void* user, double* d_pos, double* d_forces,
+                          double* d_energy)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!fn || !d_pos || !d_forces || !d_energy) return fail(c, NNP_ERR_ARG, "fn and the three buffers are required");
+    if (c->extra.size() >= 8) return fail(c, NNP_ERR_ARG, "at most 8 extra force providers");
+    c->extra.push_back({fn, user, d_pos, d_forces, d_energy});
+    c->forces_current = false;
+    c->err.clear();
+    return NNP_OK;
+}
+
+nnp_status nnp_clear_forces(nnp_context* c)
+{
+    if (!c) return NNP_ERR_ARG;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!c->extra.empty()) c->forces_current = false;
+    c->extra.clear();
     return NNP_OK;
 }
 
@@ -1285,7 +1376,7 @@ nnp_status nnp_time_kernels(nnp_context* c, int32_t reps, double* ms)
     // the timed evaluations summed their forces without a gather in between:
     // one complete evaluation leaves the forces and energies consistent
     HIP_TRY(c, enqueue_compute(c, true));
-    c->forces_current = true;
+    c->forces_current = c->extra.empty();
     c->kick_pending = false;
     return check_device_flags(c);
 }
@@ -1293,6 +1384,7 @@ nnp_status nnp_time_kernels(nnp_context* c, int32_t reps, double* ms)
 nnp_status nnp_time_steps(nnp_context* c, double dt, int32_t nsteps, double* ms)
 {
     if (!c || !ms || nsteps < 1) return fail(c, NNP_ERR_ARG, "bad arguments");
+    if (!c->extra.empty()) return fail(c, NNP_ERR_UNSUPPORTED, "timed steps cover the network only (extra forces set)");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, NNP_ERR_ARG, "dt must be finite and > 0");
     if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before stepping");
     c->diff_state = 0;
@@ -1395,6 +1487,7 @@ nnp_status nnp_autotune(nnp_context* c, const char* cache_path)
     (void)hipEventDestroy(e1);
     nnp_status s = retile(c, bestT);
     if (s != NNP_OK) return s;
+    if (!c->extra.empty()) c->forces_current = false;  // the timed evaluations had no extra forces
     nnp_status f = check_device_flags(c);
     if (f != NNP_OK) return f;
     if (cache_path) {

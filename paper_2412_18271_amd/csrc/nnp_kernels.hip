@@ -542,6 +542,48 @@ __global__ __launch_bounds__(256) void k_energy_out(Sys S, double* dst)
     if (m < S.nmol) dst[m] = S.Ecur[m];
 }
 
+// Extra force providers: positions in caller order (FP64 [n][3]) for the
+// provider, its force and energy buffers cleared.
+__global__ __launch_bounds__(256) void k_extra_prepare(Sys S, double* pos, double* frc, double* en)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < S.n) {
+        const int c = S.perm[a];
+        const double4 p = S.pos[a];
+        pos[3 * (size_t)c + 0] = p.x;
+        pos[3 * (size_t)c + 1] = p.y;
+        pos[3 * (size_t)c + 2] = p.z;
+        frc[3 * (size_t)c + 0] = 0.0;
+        frc[3 * (size_t)c + 1] = 0.0;
+        frc[3 * (size_t)c + 2] = 0.0;
+    }
+    if (a < S.nmol) en[a] = 0.0;
+}
+
+// Adds a provider's forces (caller order, eV/A) to the fixed-point force sums
+// of the running evaluation (rounded to 2^-32 eV/A like the network's) and its
+// per-molecule energies to the molecule sums.  Non-finite or too large
+// components raise the non-finite flag instead.
+__global__ __launch_bounds__(256) void k_extra_add(Sys S, const double* frc, const double* en)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < S.n) {
+        const int c = S.perm[a];
+        const double fx = frc[3 * (size_t)c], fy = frc[3 * (size_t)c + 1], fz = frc[3 * (size_t)c + 2];
+        if (fabs(fx) < (double)kFixMax && fabs(fy) < (double)kFixMax && fabs(fz) < (double)kFixMax)
+            global_force_add(S, a, __double2ll_rn(fx * kFixScale), __double2ll_rn(fy * kFixScale),
+                             __double2ll_rn(fz * kFixScale));
+        else
+            atomicOr(&S.st->nonfinite, 1);
+    }
+    if (a < S.nmol) {
+        if (isfinite(en[a]))
+            atomicAdd(&S.Eacc[a], en[a]);
+        else
+            atomicOr(&S.st->nonfinite, 1);
+    }
+}
+
 __global__ void k_invalidate_lists(Sys S)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -846,6 +888,20 @@ hipError_t launch_kickdrift(const Sys& S, double dt, hipStream_t s)
 hipError_t launch_positions_in(const Sys& S, const void* src, int is_f64, hipStream_t s)
 {
     hipLaunchKernelGGL(k_positions_in, dim3((S.n + 255) / 256), dim3(256), 0, s, S, src, is_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_extra_prepare(const Sys& S, double* pos, double* frc, double* en, hipStream_t s)
+{
+    const int n = S.n > S.nmol ? S.n : S.nmol;
+    hipLaunchKernelGGL(k_extra_prepare, dim3((n + 255) / 256), dim3(256), 0, s, S, pos, frc, en);
+    return hipGetLastError();
+}
+
+hipError_t launch_extra_add(const Sys& S, const double* frc, const double* en, hipStream_t s)
+{
+    const int n = S.n > S.nmol ? S.n : S.nmol;
+    hipLaunchKernelGGL(k_extra_add, dim3((n + 255) / 256), dim3(256), 0, s, S, frc, en);
     return hipGetLastError();
 }
 

@@ -26,6 +26,10 @@ hipError_t launch_positions_in(const Sys& S, const void* src, int is_f64, hipStr
 hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s);
 hipError_t launch_energy_out(const Sys& S, double* dst, hipStream_t s);
 hipError_t launch_invalidate_lists(const Sys& S, hipStream_t s);
+// Extra force providers: caller-order positions out and buffers cleared;
+// then their forces and energies added to the running evaluation's sums.
+hipError_t launch_extra_prepare(const Sys& S, double* pos, double* frc, double* en, hipStream_t s);
+hipError_t launch_extra_add(const Sys& S, const double* frc, const double* en, hipStream_t s);
 // E4M3 encoding of n floats by the device conversion instruction (format check).
 hipError_t launch_fp8_encode(const float* x, int n, unsigned char* out, hipStream_t s);
 hipError_t launch_descriptors_only(const Sys& S, hipStream_t s);
