@@ -79,8 +79,13 @@ __device__ __forceinline__ void env_append(Env& E, bool valid, int slot, int j, 
         const float inv = 1.0f / r;
         g = make_float4(dx * inv, dy * inv, dz * inv, r);
     }
-    const unsigned long long mR = __ballot(inR), mA = __ballot(inA);
+    const unsigned long long mR = __ballot(inR);
     const int iR = nR + lanes_below(mR);
+    // an angular entry refers to its radial entry: past the radial capacity
+    // (an overflow, reported) the neighbour is left out of both sets, so that
+    // every angular entry counted is one that was written
+    const bool keepA = inA && iR < kRadMax;
+    const unsigned long long mA = __ballot(keepA);
     const int iA = nA + lanes_below(mA);
     if (inR && iR < kRadMax) {
         E.geo[iR] = g;
@@ -95,7 +100,7 @@ __device__ __forceinline__ void env_append(Env& E, bool valid, int slot, int j, 
         }
     }
 #pragma unroll
-    for (int e = 0; e < kNumSpecies; ++e) nAs[e] += __popcll(__ballot(inA && elem == e));
+    for (int e = 0; e < kNumSpecies; ++e) nAs[e] += __popcll(__ballot(keepA && elem == e));
     nR += __popcll(mR);
     nA += __popcll(mA);
     over |= (nR > kRadMax) | (nA > kAngMax);
