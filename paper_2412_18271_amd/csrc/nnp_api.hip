@@ -854,8 +854,8 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(Ei, float*, n)
     ALLOC(Uring, double*, (size_t)kRing * nm)
     ALLOC(Kring, double*, (size_t)kRing * nm)
-    ALLOC(Eacc, double*, nm)
-    ALLOC(Kacc, double*, nm)
+    ALLOC(Eacc, double*, 2 * nm)
+    ALLOC(Kacc, double*, 2 * nm)
     ALLOC(Ecur, double*, nm)
     ALLOC(Kcur, double*, nm)
     ALLOC(perm, const int*, n)
@@ -1062,6 +1062,7 @@ nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, dou
         f4.resize(c->n);
         HIP_TRY(c, hipMemcpyAsync(f4.data(), c->S.frc, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
     }
+    HIP_TRY(c, launch_energy_flush(c->S, c->stream));
     HIP_TRY(c, hipMemcpyAsync(energy, c->S.Ecur, sizeof(double) * c->nmol, hipMemcpyDeviceToHost, c->stream));
     s = check_device_flags(c);
     if (s != NNP_OK) return s;
@@ -1218,6 +1219,7 @@ nnp_status nnp_get_state(nnp_context* c, double* pos, double* vel, double* force
         f4.resize(c->n);
         HIP_TRY(c, hipMemcpyAsync(f4.data(), c->S.frc, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
     }
+    if (pot || kin) HIP_TRY(c, launch_energy_flush(c->S, c->stream));
     if (pot) HIP_TRY(c, hipMemcpyAsync(pot, c->S.Ecur, sizeof(double) * c->nmol, hipMemcpyDeviceToHost, c->stream));
     if (kin) HIP_TRY(c, hipMemcpyAsync(kin, c->S.Kcur, sizeof(double) * c->nmol, hipMemcpyDeviceToHost, c->stream));
     nnp_status s = check_device_flags(c);
@@ -1246,6 +1248,7 @@ nnp_status nnp_get_state(nnp_context* c, double* pos, double* vel, double* force
 nnp_status nnp_energy_log(nnp_context* c, int32_t count, double* U, double* K, int32_t* written)
 {
     if (!c || !U || !K || !written || count < 0) return fail(c, NNP_ERR_ARG, "bad arguments");
+    HIP_TRY(c, launch_energy_flush(c->S, c->stream));
     StepState st;
     HIP_TRY(c, hipMemcpyAsync(&st, c->S.st, sizeof st, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -76,8 +76,10 @@ struct FragLayout {
     static constexpr int Count = B1 + 24 * 5;  // 368 fragments per element
 };
 
-// Device step state.  Written only by the last workgroup of the integration
-// kernel (completion-counter pattern), read by every kernel of the next step.
+// Device step state.  Read by every workgroup of the integration kernel at
+// its start and written by the workgroup whose arrival count shows that all
+// of them have read it (it writes at its own end, nobody waits); read by
+// every kernel of the next step.
 struct StepState {
     int step;          // steps completed
     int age;           // evaluations since the last rebuild
@@ -86,7 +88,7 @@ struct StepState {
     int overflow;      // a capacity (pair list, radial or angular LDS entries) was exceeded
     int nonfinite;     // a non-finite energy or force was produced
     int last_slot;     // step index of the most recent evaluation (ring slot = index % kRing)
-    unsigned done;     // completion counter of the integration kernel
+    unsigned started;  // workgroups of the running integration kernel that have read the state
     int max_ns, max_nr, max_na;  // largest pair-list / radial / angular count seen
     int pad;
     long long n_eval, n_rebuild, n_forced;
@@ -135,9 +137,9 @@ struct Sys {
     float* Ei;
     double* Uring;  // [kRing][nmol]
     double* Kring;
-    double* Eacc;   // [nmol] accumulators of the running evaluation
+    double* Eacc;   // [2][nmol] sums of evaluation n in Eacc[n & 1] (n = n_eval when it is gathered)
     double* Kacc;
-    double* Ecur;   // [nmol] potential / kinetic energy of the most recent evaluation
+    double* Ecur;   // [nmol] potential / kinetic energy of the most recent evaluation, after a flush
     double* Kcur;
     const int* perm;  // [n] internal -> caller index
     double* stage;    // [3 n] staging for positions in caller order

@@ -398,39 +398,76 @@ __device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, i
     bad = bad || !isfinite(e);
 }
 
-// New step state after an evaluation (nstep, age, valid, rb as the
-// evaluation saw them) and its energies; one thread.
-__device__ __forceinline__ void finish_step(const Sys& S, int mode, int nstep, int age, int valid, bool rb)
+template <typename V>
+__device__ __forceinline__ V ld_state(const V* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// New step state after an evaluation (nstep, age, valid, rb, ne as every
+// workgroup read them at entry); one thread, after all of them have read.
+__device__ __forceinline__ void finish_step(const Sys& S, int mode, int nstep, int age, int valid, bool rb,
+                                            long long ne)
 {
     StepState* st = S.st;
-    atomicAdd((unsigned long long*)&st->n_eval, 1ull);
+    st->n_eval = ne + 1;
     if (rb) {
-        atomicAdd((unsigned long long*)&st->n_rebuild, 1ull);
-        if (valid && age < S.rebuild_every) atomicAdd((unsigned long long*)&st->n_forced, 1ull);
+        st->n_rebuild += 1;
+        if (valid && age < S.rebuild_every) st->n_forced += 1;
         st->lists_valid = 1;
     }
     st->age = rb ? 1 : age + 1;
     st->viol[nstep & 1] = 0;
     st->last_slot = mode >= 1 ? nstep + 1 : nstep;
     if (mode >= 1) st->step = nstep + 1;
-    st->done = 0u;
+    st->started = 0u;
+}
+
+// Energy sums of the most recent evaluation (n_eval - 1) -> its energy-log
+// slot and Ecur / Kcur.  Idempotent; the integration kernel does the same
+// for the previous evaluation before clearing its sums.
+__device__ __forceinline__ void publish_energies(const Sys& S, long long n, int slot, int m)
+{
+    const size_t q = (size_t)(n & 1) * S.nmol + m;
+    const double em = S.Eacc[q], km = S.Kacc[q];
+    const size_t r = (size_t)(slot % kRing) * S.nmol + m;
+    S.Uring[r] = em;
+    S.Kring[r] = km;
+    S.Ecur[m] = em;
+    S.Kcur[m] = km;
 }
 
 __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, double dt, int mode, int forces)
 {
     __shared__ int last;
+    __shared__ int seen[kGatherThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63;
     const int a = blockIdx.x * kGatherThreads + tid;
     StepState* st = S.st;
-    // step state as the evaluation saw it; only the last block writes it
-    const int nstep = st->step, age = st->age, valid = st->lists_valid;
-    const bool rb = !valid || st->viol[nstep & 1] || age >= S.rebuild_every;
+    // step state as the evaluation saw it (atomic loads: read once, here)
+    const int nstep = ld_state(&st->step), age = ld_state(&st->age), valid = ld_state(&st->lists_valid);
+    const bool rb = !valid || ld_state(&st->viol[nstep & 1]) || age >= S.rebuild_every;
+    const long long ne = ld_state(&st->n_eval);
+    const int prev_slot = ld_state(&st->last_slot);
+    // Every wave stores a value computed from what it read, so its reads have
+    // returned before it reaches the barrier; then the workgroup counts itself
+    // in.  The workgroup that completes the count writes the next state at its
+    // own end: by then every workgroup has read the current one.
+    if (lane == 0) seen[tid >> 6] = nstep ^ age ^ valid ^ (int)rb ^ (int)ne ^ prev_slot;
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(&st->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == gridDim.x - 1;
+    }
+    double* Eacc = S.Eacc + (size_t)(ne & 1) * S.nmol;
+    double* Kacc = S.Kacc + (size_t)(ne & 1) * S.nmol;
     double e = 0.0, k = 0.0;
     int mol = -1;
     bool moved = false, bad = false;
     if (a < S.n) {
         mol = S.mol[a];
         integrate_atom(S, a, dt, mode, forces, nstep, e, k, moved, bad);
+        bad = bad || !isfinite(k);
     }
     if (__ballot(moved) != 0ull && lane == 0) atomicOr(&st->viol[(nstep + 1) & 1], 1);
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&st->nonfinite, 1);
@@ -447,36 +484,31 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, doub
             ks += __shfl_xor(ks, off);
         }
         if (lane == src) {
-            atomicAdd(&S.Eacc[m], es);
-            atomicAdd(&S.Kacc[m], ks);
+            atomicAdd(&Eacc[m], es);
+            atomicAdd(&Kacc[m], ks);
         }
         todo &= ~__ballot(mine);
     }
     __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&st->done, 1u);
-        last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
     if (!last) return;
-    __threadfence();
-    // the evaluation just reduced belongs to step index nstep (mode 0) or, after
-    // the kick that completes step nstep -> nstep + 1, to index nstep + 1
-    const int eval_index = mode >= 1 ? nstep + 1 : nstep;
-    const int slot = eval_index % kRing;
+    // the previous evaluation's sums (the other parity, complete since the
+    // previous launch ended) go to the energy log, then are cleared for the
+    // next evaluation, which uses that parity
     for (int m = tid; m < S.nmol; m += blockDim.x) {
-        const double em = atomic_read(&S.Eacc[m]);
-        const double km = atomic_read(&S.Kacc[m]);
-        S.Uring[(size_t)slot * S.nmol + m] = em;
-        S.Kring[(size_t)slot * S.nmol + m] = km;
-        S.Ecur[m] = em;
-        S.Kcur[m] = km;
-        if (!isfinite(em)) atomicOr(&st->nonfinite, 1);
-        __hip_atomic_store(&S.Eacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&S.Kacc[m], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ne > 0) publish_energies(S, ne - 1, prev_slot, m);
+        const size_t q = (size_t)((ne + 1) & 1) * S.nmol + m;
+        S.Eacc[q] = 0.0;
+        S.Kacc[q] = 0.0;
     }
-    if (tid == 0) finish_step(S, mode, nstep, age, valid, rb);  // from the state read at entry
+    if (tid == 0) finish_step(S, mode, nstep, age, valid, rb, ne);  // from the state read at entry
+}
+
+// Publishes the energies of the most recent evaluation (before host reads).
+__global__ __launch_bounds__(256) void k_energy_flush(Sys S)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = S.st->n_eval;
+    if (m < S.nmol && n > 0) publish_energies(S, n - 1, S.st->last_slot, m);
 }
 
 // First half kick and drift (or kick, half drift, thermostat, half drift)
@@ -539,7 +571,8 @@ __global__ __launch_bounds__(256) void k_forces_out(Sys S, double* dst)
 __global__ __launch_bounds__(256) void k_energy_out(Sys S, double* dst)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < S.nmol) dst[m] = S.Ecur[m];
+    const long long n = S.st->n_eval;
+    if (m < S.nmol) dst[m] = n > 0 ? S.Eacc[(size_t)((n - 1) & 1) * S.nmol + m] : 0.0;
 }
 
 // Extra force providers: positions in caller order (FP64 [n][3]) for the
@@ -577,8 +610,9 @@ __global__ __launch_bounds__(256) void k_extra_add(Sys S, const double* frc, con
             atomicOr(&S.st->nonfinite, 1);
     }
     if (a < S.nmol) {
+        // sums of the evaluation about to be gathered (parity of n_eval)
         if (isfinite(en[a]))
-            atomicAdd(&S.Eacc[a], en[a]);
+            atomicAdd(&S.Eacc[(size_t)(S.st->n_eval & 1) * S.nmol + a], en[a]);
         else
             atomicOr(&S.st->nonfinite, 1);
     }
@@ -908,6 +942,12 @@ hipError_t launch_extra_add(const Sys& S, const double* frc, const double* en, h
 hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_forces_out, dim3((S.n + 255) / 256), dim3(256), 0, s, S, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_flush(const Sys& S, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_flush, dim3((S.nmol + 255) / 256), dim3(256), 0, s, S);
     return hipGetLastError();
 }
 

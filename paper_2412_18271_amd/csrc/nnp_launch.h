@@ -25,6 +25,8 @@ hipError_t launch_kickdrift(const Sys& S, double dt, hipStream_t s);
 hipError_t launch_positions_in(const Sys& S, const void* src, int is_f64, hipStream_t s);
 hipError_t launch_forces_out(const Sys& S, double* dst, hipStream_t s);
 hipError_t launch_energy_out(const Sys& S, double* dst, hipStream_t s);
+// Energies of the most recent evaluation -> energy log and Ecur / Kcur.
+hipError_t launch_energy_flush(const Sys& S, hipStream_t s);
 hipError_t launch_invalidate_lists(const Sys& S, hipStream_t s);
 // Extra force providers: caller-order positions out and buffers cleared;
 // then their forces and energies added to the running evaluation's sums.
