@@ -780,12 +780,14 @@ struct PoolPlan {
 };
 
 // Group sizes, run length and lane ranges for the first nact atoms of the
-// tile (workgroup-wide; ends with a barrier).  C = ceil(W / 54 T) for W pairs in all keeps the runs within the
-// 64 T lanes: sum_g ceil(cnt_g / C) < W / C + 10 T <= 64 T.
-template <int T>
+// tile (workgroup-wide, NT threads; ends with a barrier).  C = ceil(W /
+// (NT - 10 T)) for W pairs in all keeps the runs within the NT lanes:
+// sum_g ceil(cnt_g / C) < W / C + 10 T <= NT.
+template <int T, int NT>
 __device__ __forceinline__ void pool_plan(const Env* env, int nact, PoolPlan<T>& pl, int tid)
 {
-    constexpr int NG = T * 10, FREE = 64 * T - NG;
+    constexpr int NG = T * 10, FREE = NT - NG;
+    static_assert(FREE > 0, "more lanes than groups");
     static_assert(NG <= 128, "two groups per lane of the planning wave");
     if (tid < NG && tid / 10 >= nact) pl.cnt[tid] = 0;  // no atom in this column of the tile
     if (tid < NG && tid / 10 < nact) {

@@ -41,18 +41,18 @@ struct MlpSmemOf<T, 3> {
 
 template <int T, int MODE, bool GRAD>
 __device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typename MlpSmemOf<T, MODE>::type& sm,
-                                        float* E, int tid)
+                                        float* E, int tid, int nthr = 64 * T)
 {
     const float* w = S.w32 + (size_t)elem * W32Layout::Stride;
     if constexpr (MODE == 0) {
-        mlp_f32<T, GRAD>(w, G, sm, E, tid, 64 * T);
+        mlp_f32<T, GRAD>(w, G, sm, E, tid, nthr);
     } else if constexpr (MODE == 3) {
         const long* fr = reinterpret_cast<const long*>(S.wfrag8) + (size_t)elem * FragLayout::Count * 64;
-        mlp_fp8<T, GRAD>(w, fr, S.wscale8 + 6 * elem, G, sm, E, tid, 64 * T);
+        mlp_fp8<T, GRAD>(w, fr, S.wscale8 + 6 * elem, G, sm, E, tid, nthr);
     } else {
         const bf16x8* fr = reinterpret_cast<const bf16x8*>(S.wfrag) + (size_t)elem * 2 * FragLayout::Count * 64;
-        split_g_inplace<T, MODE == 2>(G, tid, 64 * T);
-        mlp_mfma<T, MODE == 2, GRAD>(w, fr, G, sm, E, tid, 64 * T);
+        split_g_inplace<T, MODE == 2>(G, tid, nthr);
+        mlp_mfma<T, MODE == 2, GRAD>(w, fr, G, sm, E, tid, nthr);
     }
 }
 
@@ -171,17 +171,26 @@ struct PooledSmem {
     float E[16];
 };
 
+// Workgroup of the pooled kernel: 16 waves for a tile of 10 atoms.  One wave
+// per atom loads the environments; the pooled angular work, the network's
+// output-row tiles and the force merge spread over all 16.
+template <int T>
+constexpr int kPoolThreads = 1024;
+
 template <int T, int MODE, bool GRAD>
-__global__ __launch_bounds__(64 * T) void k_eval_pooled(Sys S)
+__global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
 {
+    constexpr int NT = kPoolThreads<T>;
+    static_assert(NT >= 64 * T, "a wave per atom");
     __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[blockIdx.x];
-    const bool act = wave < tile.y;
+    const bool act = wave < tile.y;  // tile.y <= T
+    const int w = wave < T ? wave : 0;
     const int a = act ? S.tile_atoms[blockIdx.x * kTileCap + wave] : 0;
     const bool rb = rebuild_due(S.st, S.rebuild_every);
-    Env& E = sm.env[wave];
-    float* Grow = sm.G + wave * kLdG;
+    Env& E = sm.env[w];
+    float* Grow = sm.G + w * kLdG;
 
     if (act) {
         if (rb && S.molgrid[S.mol[a]] < 0)
@@ -190,21 +199,21 @@ __global__ __launch_bounds__(64 * T) void k_eval_pooled(Sys S)
             load_env(S, a, E);
         if (lane == 0) S.work[a] = E.nA * (E.nA - 1) / 2 + E.nR / 2;
     }
-    for (int i = tid; i < T * kLdG; i += 64 * T) sm.G[i] = 0.f;
-    for (int i = tid; i < T * 320; i += 64 * T) sm.u.accI[i] = 0ull;
+    for (int i = tid; i < T * kLdG; i += NT) sm.G[i] = 0.f;
+    for (int i = tid; i < T * 320; i += NT) sm.u.accI[i] = 0ull;
     __syncthreads();
-    pool_plan<T>(sm.env, tile.y, sm.plan, tid);
+    pool_plan<T, NT>(sm.env, tile.y, sm.plan, tid);
     if (act) radial_features(E, Grow);
     angular_features_pooled<T>(sm.env, sm.plan, sm.u.accI, tid);
     __syncthreads();
-    angular_store_pooled<T>(sm.u.accI, sm.G, tid, 64 * T);
+    angular_store_pooled<T>(sm.u.accI, sm.G, tid, NT);
     __syncthreads();
-    run_mlp<T, MODE, GRAD>(S, tile.z, sm.G, sm.u.m, sm.E, tid);
+    run_mlp<T, MODE, GRAD>(S, tile.z, sm.G, sm.u.m, sm.E, tid, NT);
     __syncthreads();
     if (act && lane == 0) S.Ei[a] = sm.E[wave];
     if (GRAD) {
-        for (int i = tid; i < T * kAngMax * 3; i += 64 * T) sm.u.adj.faccA[i] = 0ull;
-        float* fa = sm.u.adj.facc + wave * 3 * kRadMax;
+        for (int i = tid; i < T * kAngMax * 3; i += NT) sm.u.adj.faccA[i] = 0ull;
+        float* fa = sm.u.adj.facc + w * 3 * kRadMax;
         if (act) adjoint_radial(E, Grow, fa);
         __syncthreads();
         adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.u.adj.faccA, tid);
@@ -212,11 +221,11 @@ __global__ __launch_bounds__(64 * T) void k_eval_pooled(Sys S)
         // merge the tile's forces per receiving atom in the G rows (dE/dG is
         // no longer read)
         const ForceTable ft = force_table(sm.G, sizeof(sm.G));
-        table_clear(ft, tid, 64 * T);
+        table_clear(ft, tid, NT);
         __syncthreads();
         if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.u.adj.faccA + (size_t)wave * kAngMax * 3);
         __syncthreads();
-        table_flush(S, ft, tid, 64 * T);
+        table_flush(S, ft, tid, NT);
     }
 }
 
@@ -805,7 +814,8 @@ template <int T, int MODE, bool GRAD>
 static hipError_t launch_fused_t(const Sys& S, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if constexpr (kPooledTile<T>)
-        hipExtLaunchKernelGGL((k_eval_pooled<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, ev0, ev1, 0, S);
+        hipExtLaunchKernelGGL((k_eval_pooled<T, MODE, GRAD>), dim3(S.ntiles), dim3(kPoolThreads<T>), 0, s, ev0, ev1, 0,
+                              S);
     else
         hipExtLaunchKernelGGL((k_eval_fused<T, MODE, GRAD>), dim3(S.ntiles), dim3(64 * T), 0, s, ev0, ev1, 0, S);
     return hipGetLastError();
