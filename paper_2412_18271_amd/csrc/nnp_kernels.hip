@@ -155,10 +155,16 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
 
 // Fused evaluation with the angular work of the tile pooled over all lanes of
 // the workgroup (see PoolPlan): same stages and outputs as k_eval_fused.
+// LDS left over by the pooled kernel's other buffers (one workgroup per CU)
+// widens the workgroup's force-merge table: clumped tiles reach several
+// hundred distinct receiving atoms, and a nearly full table probes long.
+constexpr int kPoolTableExtra = 10240;  // floats
+
 template <int T, int MODE>
 struct PooledSmem {
     Env env[T];
     float G[T * kLdG];
+    float Gx[kPoolTableExtra];  // continues G for the force-merge table only
     PoolPlan<T> plan;
     union __attribute__((aligned(16))) {  // 16-byte LDS vector accesses
         typename MlpSmemOf<T, MODE>::type m;
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
         __syncthreads();
         // merge the tile's forces per receiving atom in the G rows (dE/dG is
         // no longer read)
-        const ForceTable ft = force_table(sm.G, sizeof(sm.G));
+        const ForceTable ft = force_table(sm.G, sizeof(sm.G) + sizeof(sm.Gx));
         table_clear(ft, tid, NT);
         __syncthreads();
         if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.u.adj.faccA + (size_t)wave * kAngMax * 3);
