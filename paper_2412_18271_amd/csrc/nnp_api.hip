@@ -850,7 +850,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(work, int*, n)
     ALLOC(nbr, int*, n * cap)
     ALLOC(ncnt, int*, n)
-    ALLOC(facc, unsigned long long*, 4 * (size_t)n)
+    ALLOC(facc, unsigned long long*, (size_t)kFaccCopies * 4 * n)
     ALLOC(Ei, float*, n)
     ALLOC(Uring, double*, (size_t)kRing * nm)
     ALLOC(Kring, double*, (size_t)kRing * nm)

@@ -9,10 +9,11 @@
 //   frc    double4[n]    gathered FP64 forces (eV/A)
 //   ref    float4[n]     positions at the last pair-list rebuild
 //   nbr    int[n][cap]   pair list (cutoff 5.2 + skin), ascending internal index
-//   facc   int64[n][4]   force accumulators of the running evaluation, fixed
-//                        point with 2^-32 eV/A resolution (x, y, z, unused);
-//                        integer addition makes the sum independent of the
-//                        order of the atomic adds
+//   facc   int64[kFaccCopies][n][4] force accumulators of the running evaluation, fixed
+//                        point with 2^-32 eV/A resolution (x, y, z, unused),
+//                        one copy per die (accelerator complex); integer
+//                        addition makes the sum independent of the order of
+//                        the atomic adds and of the copies
 //   Ei     float[n]      per-atom energies of the last evaluation
 #pragma once
 
@@ -44,6 +45,7 @@ constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits
 constexpr int kRing = 4096;   // energy log ring (steps)
 constexpr int kXcds = 8;      // accelerator complex dies; workgroups go round-robin
 constexpr int kTileCap = 16;  // largest atoms-per-tile (MFMA columns)
+constexpr int kFaccCopies = 4;  // copies of the force sums: workgroup b (on die b mod 8) adds into copy b mod 4
 
 // Per-element FP32 weight block (floats).  Forward dense layers read the
 // transposed matrices ([in][out], coalesced over outputs), the backward ones
@@ -133,7 +135,7 @@ struct Sys {
     int* work;              // [n] angular pairs + radial entries / 2 at the last evaluation
     int* nbr;
     int* ncnt;
-    unsigned long long* facc;  // [n][4] fixed-point forces, zero between evaluations
+    unsigned long long* facc;  // [kFaccCopies][n][4] fixed-point forces, zero between evaluations
     float* Ei;
     double* Uring;  // [kRing][nmol]
     double* Kring;

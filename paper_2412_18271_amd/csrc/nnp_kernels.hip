@@ -56,6 +56,17 @@ __device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typena
     }
 }
 
+// The evaluation kernels add forces into one of kFaccCopies copies of the
+// fixed-point sums, chosen by the die their workgroup runs on (workgroup b
+// -> die b mod 8 -> copy b mod 4: dies whose tiles lie far apart share a
+// copy), so that the hot atoms of a clump are not updated by every die at
+// one address; the integration kernel adds the copies.  Four copies beat
+// eight (the integration kernel reads and clears each) and one.
+__device__ __forceinline__ void use_die_copy(Sys& S)
+{
+    S.facc += (size_t)(blockIdx.x % kFaccCopies) * 4 * (size_t)S.n;
+}
+
 template <int T, int MODE>
 struct FusedSmem {
     Env env[T];
@@ -71,6 +82,7 @@ struct FusedSmem {
 template <int T, int MODE, bool GRAD>
 __global__ __launch_bounds__(64 * T) void k_eval_fused(Sys S)
 {
+    use_die_copy(S);
     __shared__ __attribute__((aligned(16))) FusedSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[blockIdx.x];
@@ -188,6 +200,7 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
 {
     constexpr int NT = kPoolThreads<T>;
     static_assert(NT >= 64 * T, "a wave per atom");
+    use_die_copy(S);
     __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[blockIdx.x];
@@ -263,6 +276,7 @@ __global__ __launch_bounds__(64 * T) void k_mlp(Sys S)
 // Adjoint of all atoms from S.dG.  One wave per atom.
 __global__ __launch_bounds__(256) void k_adjoint(Sys S)
 {
+    use_die_copy(S);
     __shared__ Env env[4];
     __shared__ __attribute__((aligned(16))) float g[4 * kNumFeat];
     __shared__ float facc[4 * 3 * kRadMax];
@@ -373,8 +387,21 @@ __device__ __forceinline__ void drift_atom(const Sys& S, double dt, double ki, d
 __device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, int mode, int forces, int nstep,
                                                double& e, double& k, bool& moved, bool& bad)
 {
-    unsigned long long* fa = S.facc + 4 * (size_t)a;
-    const unsigned long long qx = fa[0], qy = fa[1], qz = fa[2];
+    // the sums of the copies (integer: order-independent), each cleared
+    unsigned long long qx = 0ull, qy = 0ull, qz = 0ull;
+    ulonglong2 c01[kFaccCopies], c23[kFaccCopies];
+#pragma unroll
+    for (int x = 0; x < kFaccCopies; ++x) {
+        const ulonglong2* f = reinterpret_cast<const ulonglong2*>(S.facc + ((size_t)x * S.n + a) * 4);
+        c01[x] = f[0];
+        c23[x] = f[1];
+    }
+#pragma unroll
+    for (int x = 0; x < kFaccCopies; ++x) {
+        qx += c01[x].x;
+        qy += c01[x].y;
+        qz += c23[x].x;
+    }
     double4 v = S.vel[a];
     const double ki = S.kinv[a];
     e = (double)S.Ei[a];
@@ -387,9 +414,12 @@ __device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, i
         // noise of the next step, computed while the loads above are in flight
         if (S.gamma > 0.0) z = langevin_noise(S.seed, S.perm[a], nstep + 1);
     }
-    fa[0] = 0ull;
-    fa[1] = 0ull;
-    fa[2] = 0ull;
+#pragma unroll
+    for (int x = 0; x < kFaccCopies; ++x) {
+        ulonglong2* f = reinterpret_cast<ulonglong2*>(S.facc + ((size_t)x * S.n + a) * 4);
+        f[0] = make_ulonglong2(0ull, 0ull);
+        f[1] = make_ulonglong2(0ull, 0ull);
+    }
     const double fx = (double)(long long)qx * (1.0 / kFixScale);
     const double fy = (double)(long long)qy * (1.0 / kFixScale);
     const double fz = (double)(long long)qz * (1.0 / kFixScale);
