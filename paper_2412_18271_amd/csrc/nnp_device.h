@@ -780,45 +780,48 @@ struct PoolPlan {
 };
 
 // Group sizes, run length and lane ranges for the first nact atoms of the
-// tile (workgroup-wide, NT threads; ends with a barrier).  C = ceil(W /
-// (NT - 10 T)) for W pairs in all keeps the runs within the NT lanes:
-// sum_g ceil(cnt_g / C) < W / C + 10 T <= NT.
+// tile, computed by one wave (lane: groups 2 lane and 2 lane + 1) while the
+// others do other work; the caller's next barrier publishes the plan.
+// C = ceil(W / (NT - 10 T)) for W pairs in all keeps the runs within the NT
+// lanes of the workgroup: sum_g ceil(cnt_g / C) < W / C + 10 T <= NT.
 template <int T, int NT>
-__device__ __forceinline__ void pool_plan(const Env* env, int nact, PoolPlan<T>& pl, int tid)
+__device__ __forceinline__ void pool_plan_wave(const Env* env, int nact, PoolPlan<T>& pl, int lane)
 {
     constexpr int NG = T * 10, FREE = NT - NG;
     static_assert(FREE > 0, "more lanes than groups");
     static_assert(NG <= 128, "two groups per lane of the planning wave");
-    if (tid < NG && tid / 10 >= nact) pl.cnt[tid] = 0;  // no atom in this column of the tile
-    if (tid < NG && tid / 10 < nact) {
-        const Env& E = env[tid / 10];
-        const int p = tid % 10;
+    auto group_size = [&](int g) {
+        if (g >= NG || g / 10 >= nact) return 0;  // no atom in this column of the tile
+        const Env& E = env[g / 10];
+        const int p = g % 10;
         const int s1 = kPairS1[p], s2 = kPairS2[p];
         const int n1 = E.aseg[s1 + 1] - E.aseg[s1], n2 = E.aseg[s2 + 1] - E.aseg[s2];
-        pl.cnt[tid] = s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        const int g0 = 2 * tid, g1 = 2 * tid + 1;
-        const int c0 = g0 < NG ? pl.cnt[g0] : 0, c1 = g1 < NG ? pl.cnt[g1] : 0;
-        int w = c0 + c1;
+        return s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
+    };
+    const int g0 = 2 * lane, g1 = 2 * lane + 1;
+    const int c0 = group_size(g0), c1 = group_size(g1);
+    int w = c0 + c1;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
-        const int C = w > FREE ? (w + FREE - 1) / FREE : 1;
-        const int r0 = (c0 + C - 1) / C, r1 = (c1 + C - 1) / C;
-        int incl = r0 + r1;
+    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+    const int C = w > FREE ? (w + FREE - 1) / FREE : 1;
+    const int r0 = (c0 + C - 1) / C, r1 = (c1 + C - 1) / C;
+    int incl = r0 + r1;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off);
-            if (tid >= off) incl += v;
-        }
-        const int excl = incl - r0 - r1;
-        if (g0 < NG) pl.first[g0] = excl;
-        if (g1 < NG) pl.first[g1] = excl + r0;
-        if (tid == 63) pl.first[NG] = incl;
-        if (tid == 0) pl.C = C;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
     }
-    __syncthreads();
+    const int excl = incl - r0 - r1;
+    if (g0 < NG) {
+        pl.cnt[g0] = c0;
+        pl.first[g0] = excl;
+    }
+    if (g1 < NG) {
+        pl.cnt[g1] = c1;
+        pl.first[g1] = excl + r0;
+    }
+    if (lane == 63) pl.first[NG] = incl;
+    if (lane == 0) pl.C = C;
 }
 
 // The run of workgroup lane L (R.p < 0 when L has none); w = its atom.

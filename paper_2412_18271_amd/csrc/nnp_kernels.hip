@@ -199,7 +199,7 @@ template <int T, int MODE, bool GRAD>
 __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
 {
     constexpr int NT = kPoolThreads<T>;
-    static_assert(NT >= 64 * T, "a wave per atom");
+    static_assert(NT > 64 * T, "a wave per atom and a planning wave");
     use_die_copy(S);
     __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -221,8 +221,11 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
     for (int i = tid; i < T * kLdG; i += NT) sm.G[i] = 0.f;
     for (int i = tid; i < T * 320; i += NT) sm.u.accI[i] = 0ull;
     __syncthreads();
-    pool_plan<T, NT>(sm.env, tile.y, sm.plan, tid);
+    // the last wave (never an atom's: NT > 64 T) plans the pooled runs while
+    // the atoms' waves compute their radial features
+    if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
     if (act) radial_features(E, Grow);
+    __syncthreads();
     angular_features_pooled<T>(sm.env, sm.plan, sm.u.accI, tid);
     __syncthreads();
     angular_store_pooled<T>(sm.u.accI, sm.G, tid, NT);
