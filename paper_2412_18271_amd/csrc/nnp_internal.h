@@ -45,7 +45,7 @@ constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits
 constexpr int kRing = 4096;   // energy log ring (steps)
 constexpr int kXcds = 8;      // accelerator complex dies; workgroups go round-robin
 constexpr int kTileCap = 16;  // largest atoms-per-tile (MFMA columns)
-constexpr int kFaccCopies = 4;  // copies of the force sums: workgroup b (on die b mod 8) adds into copy b mod 4
+constexpr int kFaccCopies = 4;  // copies of the force sums: workgroup b adds into copy (b / 8) mod 4
 
 // Per-element FP32 weight block (floats).  Forward dense layers read the
 // transposed matrices ([in][out], coalesced over outputs), the backward ones

@@ -57,14 +57,16 @@ __device__ __forceinline__ void run_mlp(const Sys& S, int elem, float* G, typena
 }
 
 // The evaluation kernels add forces into one of kFaccCopies copies of the
-// fixed-point sums, chosen by the die their workgroup runs on (workgroup b
-// -> die b mod 8 -> copy b mod 4: dies whose tiles lie far apart share a
-// copy), so that the hot atoms of a clump are not updated by every die at
-// one address; the integration kernel adds the copies.  Four copies beat
-// eight (the integration kernel reads and clears each) and one.
+// fixed-point sums, so that the hot atoms of a clump are not updated by
+// every workgroup at one address; the integration kernel adds the copies.
+// Workgroup b runs on die b mod 8, and each die takes a contiguous run of
+// tiles (neighbouring tiles sit on one die, b apart by multiples of 8):
+// copy (b / 8) mod 4 gives consecutive tiles of a die different copies.
+// Four copies beat eight (the integration kernel reads and clears each) and
+// one; this assignment beats copy = b mod 4.
 __device__ __forceinline__ void use_die_copy(Sys& S)
 {
-    S.facc += (size_t)(blockIdx.x % kFaccCopies) * 4 * (size_t)S.n;
+    S.facc += (size_t)((blockIdx.x / kXcds) % kFaccCopies) * 4 * (size_t)S.n;
 }
 
 template <int T, int MODE>
