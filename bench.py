@@ -27,7 +27,9 @@ average duration of the evaluation kernel for the roofline report.
 Other modes (not part of the default run): --precision (errors per network
 dtype on a second 2,500-atom cluster and on 23,000 atoms, and NVE drift),
 --profile-only (one variant's steps, for rocprofv3), --pmc-summary (turns
-two rocprofv3 counter databases into the traffic summary kept in profiles/).
+two rocprofv3 counter databases into the traffic summary kept in profiles/),
+--counter-summary (per-kernel counters of one variant: MFMA utilisation and
+rate, vector-ALU and LDS activity, HBM rate, as a markdown section).
 
 Prints ONE JSON line on stdout.
 """
@@ -333,6 +335,75 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     print("\n".join(lines))
 
 
+def counter_summary(variant, stats_csv, dbs, mib):
+    """Markdown section for one variant: per kernel, its mean duration (from a
+    kernel-trace statistics file of the same variant) and the mean value per
+    dispatch of every counter in the rocprofv3 counter databases, with the
+    MFMA rate against the dtype's dense peak and, where FETCH_SIZE and
+    WRITE_SIZE were taken next to the calibration kernel, the HBM rate
+    against 8 TB/s."""
+    import csv
+    dtype, path = variant.split(":")
+    dur = {}
+    with open(stats_csv) as fh:
+        for row in csv.DictReader(fh):
+            dur[row["Name"]] = (float(row["AverageNs"]), int(row["Calls"]))
+    vals, names, passes = {}, {}, []
+    known_kib = mib * 1024.0
+    scale = {}
+    for db in dbs:
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+        c.close()
+        passes.append(sorted({r[1] for r in rows}))
+        for k, n, v in rows:
+            if "neg" in k and n in ("FETCH_SIZE", "WRITE_SIZE") and v > 0.25 * known_kib:
+                scale.setdefault(n, []).append(v)
+            if not re.search(r"nnp::k_", k):
+                continue
+            vals.setdefault(k, {}).setdefault(n, []).append(float(v))
+            names[n] = True
+    factor = {n: known_kib / float(np.median(v)) for n, v in scale.items()}
+    counters = list(names)
+    mfma_peak = MI355X_FP8_MFMA_TFLOPS if dtype == "fp8" else MI355X_BF16_MFMA_TFLOPS
+    head = ["kernel", "mean us (trace)", "dispatches"] + counters
+    derived = []
+    if "MfmaFlopsBF16" in names:
+        head += ["MFMA TFLOP/s", "of %g" % mfma_peak]
+        derived.append("mfma")
+    if "FETCH_SIZE" in factor and "WRITE_SIZE" in factor:
+        head += ["HBM bytes (scaled)", "GB/s", "of 8000"]
+        derived.append("hbm")
+    out = ["## %s network, %s path" % (dtype, path), "",
+           "Counter passes (one rocprofv3 run each, `--profile-only %s --steps 20 --warmup 5`):" % variant, ""]
+    out += ["- `%s`" % " ".join(p) for p in passes]
+    if factor:
+        out += ["", "HBM counters scaled by the calibration kernel (torch.neg over %d MiB): %s." % (
+            mib, ", ".join("%s x %.3f" % kv for kv in sorted(factor.items())))]
+    out += ["", "| " + " | ".join(head) + " |", "|" + "---|" * len(head)]
+    order = sorted(vals, key=lambda k: -dur.get(k, (0.0, 0))[0])
+    for k in order:
+        us = dur.get(k, (float("nan"), 0))[0] / 1e3
+        row = [k.replace("nnp::", "").replace("(nnp::Sys)", "").split("(")[0], "%.2f" % us,
+               str(len(next(iter(vals[k].values()))))]
+        mean = {n: float(np.mean(v)) for n, v in vals[k].items()}
+        row += ["%.4g" % mean[n] if n in mean else "" for n in counters]
+        if "mfma" in derived:
+            f = mean.get("MfmaFlopsBF16", 0.0)
+            t = f / (us * 1e-6) / 1e12 if us == us and us > 0 else float("nan")
+            row += ["%.1f" % t, "%.2f %%" % (100 * t / mfma_peak)]
+        if "hbm" in derived:
+            if "FETCH_SIZE" in mean and "WRITE_SIZE" in mean:
+                b = (mean["FETCH_SIZE"] * factor["FETCH_SIZE"] + mean["WRITE_SIZE"] * factor["WRITE_SIZE"]) * 1024
+                g = b / (us * 1e-6) / 1e9 if us == us and us > 0 else float("nan")
+                row += ["%.0f" % b, "%.0f" % g, "%.2f %%" % (100 * g / MI355X_HBM_GBS)]
+            else:
+                row += ["", "", ""]
+        out.append("| " + " | ".join(row) + " |")
+    out.append("")
+    print("\n".join(out))
+
+
 def load_traffic(variant):
     """HBM bytes per launch from the committed counter summary, or None when
     it covers another variant or the kernel sources changed since."""
@@ -456,6 +527,9 @@ def main():
     ap.add_argument("--pmc-command", default="timeout -s KILL 60 rocprofv3 --pmc COUNTER -d <dir> -o run -- "
                     "python3 bench.py --profile-only bf16x3:fused --steps 20 --warmup 5 "
                     "--copy-calibration-mib 256")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DB", default=None,
+                    help="rocprofv3 counter databases of one variant (--variant) -> markdown section")
+    ap.add_argument("--trace-stats", default=None, help="with --counter-summary: kernel_stats.csv of the variant")
     ap.add_argument("--precision", action="store_true",
                     help="run the precision / drift study instead of the benchmark")
     ap.add_argument("--drift-steps", type=int, default=10000)
@@ -468,6 +542,10 @@ def main():
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.variant,
                     args.copy_calibration_mib or 256, args.pmc_command)
+        return
+
+    if args.counter_summary:
+        counter_summary(args.variant, args.trace_stats, args.counter_summary, args.copy_calibration_mib or 256)
         return
 
     import synth
