@@ -335,7 +335,7 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     print("\n".join(lines))
 
 
-def counter_summary(variant, stats_csv, dbs, mib):
+def counter_summary(variant, stats_csv, dbs, mib, profile_args):
     """Markdown section for one variant: per kernel, its mean duration (from a
     kernel-trace statistics file of the same variant) and the mean value per
     dispatch of every counter in the rocprofv3 counter databases, with the
@@ -375,7 +375,7 @@ def counter_summary(variant, stats_csv, dbs, mib):
         head += ["HBM bytes (scaled)", "GB/s", "of 8000"]
         derived.append("hbm")
     out = ["## %s network, %s path" % (dtype, path), "",
-           "Counter passes (one rocprofv3 run each, `--profile-only %s --steps 20 --warmup 5`):" % variant, ""]
+           "Counter passes (one rocprofv3 run each, `--profile-only %s %s`):" % (variant, profile_args), ""]
     out += ["- `%s`" % " ".join(p) for p in passes]
     if factor:
         out += ["", "HBM counters scaled by the calibration kernel (torch.neg over %d MiB): %s." % (
@@ -530,6 +530,8 @@ def main():
     ap.add_argument("--counter-summary", nargs="+", metavar="DB", default=None,
                     help="rocprofv3 counter databases of one variant (--variant) -> markdown section")
     ap.add_argument("--trace-stats", default=None, help="with --counter-summary: kernel_stats.csv of the variant")
+    ap.add_argument("--profile-args", default="--steps 200 --warmup 20",
+                    help="with --counter-summary: the --profile-only arguments the runs used")
     ap.add_argument("--precision", action="store_true",
                     help="run the precision / drift study instead of the benchmark")
     ap.add_argument("--drift-steps", type=int, default=10000)
@@ -545,7 +547,8 @@ def main():
         return
 
     if args.counter_summary:
-        counter_summary(args.variant, args.trace_stats, args.counter_summary, args.copy_calibration_mib or 256)
+        counter_summary(args.variant, args.trace_stats, args.counter_summary, args.copy_calibration_mib or 256,
+                        args.profile_args)
         return
 
     import synth
