@@ -134,6 +134,14 @@ __device__ __forceinline__ void env_finish(const Sys& S, Env& E, int nR, int nA,
 // of them is tested (the scan is bound by load latency, not arithmetic).
 constexpr int kScanUnroll = 4;
 
+// Pair-list test of a displacement (nearest image), with the same rounding
+// wherever a list is built from a candidate scan.
+__device__ __forceinline__ bool in_pair_list(const Sys& S, double dx, double dy, double dz)
+{
+    min_image(S, dx, dy, dz);
+    return fma(dz, dz, fma(dy, dy, dx * dx)) < (double)S.rlist2;
+}
+
 // Builds only the pair list.
 __device__ __forceinline__ void build_list(const Sys& S, int a)
 {
@@ -155,12 +163,7 @@ __device__ __forceinline__ void build_list(const Sys& S, int a)
             for (int u = 0; u < kScanUnroll; ++u) {
                 if (c0 + 64 * u >= rg.y) break;  // wave-uniform
                 const int c = c0 + 64 * u + lane;
-                bool ok = false;
-                if (c < rg.y && c != a) {
-                    double dx = pc[u].x - pa.x, dy = pc[u].y - pa.y, dz = pc[u].z - pa.z;
-                    min_image(S, dx, dy, dz);
-                    ok = dx * dx + dy * dy + dz * dz < (double)S.rlist2;
-                }
+                const bool ok = c < rg.y && c != a && in_pair_list(S, pc[u].x - pa.x, pc[u].y - pa.y, pc[u].z - pa.z);
                 const unsigned long long mk = __ballot(ok);
                 const int slot = count + lanes_below(mk);
                 if (ok && slot < S.cap) S.nbr[base + slot] = c;
@@ -171,6 +174,108 @@ __device__ __forceinline__ void build_list(const Sys& S, int a)
     if (lane == 0) {
         S.ncnt[a] = count < S.cap ? count : S.cap;
         S.ref[a] = make_float4((float)pa.x, (float)pa.y, (float)pa.z, 0.f);
+        if (count > S.cap) atomicOr(&S.st->overflow, 1);
+    }
+}
+
+// Pair-list rebuild shared by the atoms of a tile when they all belong to one
+// molecule scanned without a cell grid.  The workgroup reads each of the
+// molecule's atoms once and applies build_list's test against every atom of
+// the tile, keeping, in ascending index order, the atoms that pass for at
+// least one of them with a mask of those it passes for; each atom's wave
+// then writes its list from the kept atoms that carry its bit: the same
+// candidates, tested by the same function in the same order, as build_list.
+constexpr int kSharedScanCap = 4096;
+
+struct SharedScan {
+    int idx[kSharedScanCap];       // kept atoms, ascending
+    unsigned mask[kSharedScanCap]; // bit i: within the list radius of tile atom i
+    double tx[kTileCap], ty[kTileCap], tz[kTileCap];
+    int ta[kTileCap];
+};
+
+// Number of kept atoms, or -1 (nothing kept, workgroup-uniform) when the
+// tile spans molecules, the molecule has a cell grid or more than
+// kSharedScanCap atoms.  All threads of the workgroup call it.
+template <int NT>
+__device__ __forceinline__ int shared_scan(const Sys& S, const int* atoms, int cnt, SharedScan& sc, int* wcnt,
+                                           int tid)
+{
+    const int m = S.mol[atoms[0]];
+    if (S.molgrid[m] >= 0) return -1;
+    for (int i = 1; i < cnt; ++i)
+        if (S.mol[atoms[i]] != m) return -1;
+    int2 rg[kNumSpecies];
+    int cum[kNumSpecies + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int e = 0; e < kNumSpecies; ++e) {
+        rg[e] = S.mrange[m * kNumSpecies + e];
+        cum[e + 1] = cum[e] + (rg[e].y - rg[e].x);
+    }
+    const int total = cum[kNumSpecies];
+    if (total > kSharedScanCap) return -1;
+    if (tid < cnt) {
+        const int a = atoms[tid];
+        const double4 p = S.pos[a];
+        sc.tx[tid] = p.x;
+        sc.ty[tid] = p.y;
+        sc.tz[tid] = p.z;
+        sc.ta[tid] = a;
+    }
+    __syncthreads();
+    const int wave = tid >> 6;
+    int nl = 0;
+    for (int q0 = 0; q0 < total; q0 += NT) {
+        const int q = q0 + tid;
+        unsigned mk = 0;
+        int c = 0;
+        if (q < total) {
+#pragma unroll
+            for (int e = 0; e < kNumSpecies; ++e)
+                if (q >= cum[e] && q < cum[e + 1]) c = rg[e].x + (q - cum[e]);
+            const double4 pc = S.pos[c];
+            for (int i = 0; i < cnt; ++i)
+                if (c != sc.ta[i] && in_pair_list(S, pc.x - sc.tx[i], pc.y - sc.ty[i], pc.z - sc.tz[i]))
+                    mk |= 1u << i;
+        }
+        const unsigned long long bal = __ballot(mk != 0);
+        if ((tid & 63) == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int off = nl, tot = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            if (w < wave) off += wcnt[w];
+            tot += wcnt[w];
+        }
+        if (mk != 0) {
+            const int slot = off + lanes_below(bal);
+            sc.idx[slot] = c;
+            sc.mask[slot] = mk;
+        }
+        nl += tot;
+        __syncthreads();  // wcnt is rewritten by the next chunk
+    }
+    return nl;
+}
+
+// Pair list of atom a, column `bit` of its tile, from the atoms kept by
+// shared_scan.
+__device__ __forceinline__ void build_list_shared(const Sys& S, int a, int bit, const SharedScan& sc, int nl)
+{
+    const int lane = lane_id();
+    int count = 0;
+    const size_t base = (size_t)a * S.cap;
+    for (int s0 = 0; s0 < nl; s0 += 64) {
+        const int s = s0 + lane;
+        const bool ok = s < nl && ((sc.mask[s] >> bit) & 1u);
+        const unsigned long long mk = __ballot(ok);
+        const int slot = count + lanes_below(mk);
+        if (ok && slot < S.cap) S.nbr[base + slot] = sc.idx[s];
+        count += __popcll(mk);
+    }
+    if (lane == 0) {
+        S.ncnt[a] = count < S.cap ? count : S.cap;
+        S.ref[a] = make_float4((float)sc.tx[bit], (float)sc.ty[bit], (float)sc.tz[bit], 0.f);
         if (count > S.cap) atomicOr(&S.st->overflow, 1);
     }
 }

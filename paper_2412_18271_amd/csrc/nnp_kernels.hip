@@ -15,6 +15,8 @@
 #include "nnp_device.h"
 #include <hip/hip_ext.h>
 
+#include <cstddef>
+
 #include "nnp_launch.h"
 
 namespace nnp {
@@ -189,6 +191,7 @@ struct PooledSmem {
         } adj;
     } u;
     float E[16];
+    int wcnt[16];  // per-wave counts of the shared candidate scan
 };
 
 // Workgroup of the pooled kernel: 16 waves for a tile of 10 atoms.  One wave
@@ -213,13 +216,29 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
     Env& E = sm.env[w];
     float* Grow = sm.G + w * kLdG;
 
+    // a rebuild scans the molecule once for the whole tile when it can; the
+    // candidates overlay G and Gx until the barrier below
+    using Smem = PooledSmem<T, MODE>;
+    static_assert(offsetof(Smem, Gx) == offsetof(Smem, G) + sizeof(sm.G) &&
+                  sizeof(SharedScan) <= sizeof(sm.G) + sizeof(sm.Gx) && offsetof(Smem, G) % 16 == 0,
+                  "candidate list over G and Gx");
+    SharedScan& scan = *reinterpret_cast<SharedScan*>(sm.G);
+    const int nl = rb ? shared_scan<NT>(S, S.tile_atoms + blockIdx.x * kTileCap, tile.y, scan, sm.wcnt, tid) : -1;
     if (act) {
-        if (rb && S.molgrid[S.mol[a]] < 0)
-            build_list_env(S, a, E);
-        else
+        if (rb && S.molgrid[S.mol[a]] < 0) {
+            if (nl >= 0) {
+                build_list_shared(S, a, wave, scan, nl);
+                __threadfence_block();
+                load_env(S, a, E);
+            } else {
+                build_list_env(S, a, E);
+            }
+        } else {
             load_env(S, a, E);
+        }
         if (lane == 0) S.work[a] = E.nA * (E.nA - 1) / 2 + E.nR / 2;
     }
+    if (nl >= 0) __syncthreads();
     for (int i = tid; i < T * kLdG; i += NT) sm.G[i] = 0.f;
     for (int i = tid; i < T * 320; i += NT) sm.u.accI[i] = 0ull;
     __syncthreads();
