@@ -50,6 +50,7 @@ struct nnp_context {
     // tiles on the host: table and the atom of every column (kTileCap per tile)
     std::vector<int4> tiles;
     std::vector<int> tile_atoms;
+    std::vector<int> molgrid;  // grid of each molecule, -1: scanned without a cell grid
     nnp_dtype dtype = NNP_MLP_FP32;
     nnp_path path = NNP_PATH_FUSED;
     int rebuild_every = 20;
@@ -221,6 +222,29 @@ std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
     return out;
 }
 
+// Molecule of every tile for the pair-list rebuild shared by a tile's atoms:
+// m when all of the tile's atoms belong to molecule m, m is scanned without
+// a cell grid and has at most kSharedScanCap atoms, else -1 (each atom then
+// scans for itself).  Needed whenever the tiles' atoms or the grids change.
+// Synchronous.
+nnp_status upload_tile_mol(nnp_context* c)
+{
+    if (c->tiles.empty() || c->molgrid.size() != (size_t)c->nmol || c->perm.size() != (size_t)c->n ||
+        c->tile_atoms.size() != c->tiles.size() * kTileCap)
+        return NNP_OK;
+    std::vector<int> tm(c->tiles.size(), -1);
+    for (size_t b = 0; b < c->tiles.size(); ++b) {
+        const int* col = c->tile_atoms.data() + b * kTileCap;
+        const int m = c->mol_of[c->perm[col[0]]];
+        bool one = c->molgrid[m] < 0 && c->mol_offsets[m + 1] - c->mol_offsets[m] <= kSharedScanCap;
+        for (int i = 1; i < c->tiles[b].y && one; ++i) one = c->mol_of[c->perm[col[i]]] == m;
+        tm[b] = one ? m : -1;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy((void*)c->S.tile_mol, tm.data(), sizeof(int) * tm.size(), hipMemcpyHostToDevice));
+    return NNP_OK;
+}
+
 // Tile table and column atoms (the initial tiling: consecutive atoms) to the
 // device.  Synchronous.
 nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
@@ -233,7 +257,7 @@ nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
     HIP_TRY(c, hipMemcpy((void*)c->S.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy((void*)c->S.tile_atoms, c->tile_atoms.data(), sizeof(int) * c->tile_atoms.size(),
                          hipMemcpyHostToDevice));
-    return NNP_OK;
+    return upload_tile_mol(c);
 }
 
 // Tiles whose atoms pool their angular work (10 per tile) take as long as
@@ -285,7 +309,7 @@ nnp_status rebalance_tiles(nnp_context* c)
         HIP_TRY(c, hipMemcpyAsync((void*)c->S.tile_atoms, c->tile_atoms.data(), sizeof(int) * c->tile_atoms.size(),
                                   hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return NNP_OK;
+    return changed ? upload_tile_mol(c) : NNP_OK;
 }
 
 // Cell grids of the molecules with more than kBruteMax atoms (the others scan
@@ -381,7 +405,8 @@ nnp_status setup_grids(nnp_context* c, const double* pos)
     S.ncells = (int)ncells;
     if (ncells > 0)
         HIP_TRY(c, hipMemcpy((void*)S.grids, grids.data(), sizeof(CellGrid) * grids.size(), hipMemcpyHostToDevice));
-    return NNP_OK;
+    c->molgrid = molgrid;
+    return upload_tile_mol(c);
 }
 
 // Builds the internal order from the first positions and uploads every
@@ -847,6 +872,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     ALLOC(mrange, const int2*, nm * 4)
     ALLOC(tiles, const int4*, n)
     ALLOC(tile_atoms, const int*, (size_t)n * kTileCap)
+    ALLOC(tile_mol, const int*, n)
     ALLOC(work, int*, n)
     ALLOC(nbr, int*, n * cap)
     ALLOC(ncnt, int*, n)

@@ -185,26 +185,27 @@ __device__ __forceinline__ void build_list(const Sys& S, int a)
 // least one of them with a mask of those it passes for; each atom's wave
 // then writes its list from the kept atoms that carry its bit: the same
 // candidates, tested by the same function in the same order, as build_list.
-constexpr int kSharedScanCap = 4096;
+constexpr int kScanRoundsMax = 4;  // kSharedScanCap / 1024 threads
 
 struct SharedScan {
     int idx[kSharedScanCap];       // kept atoms, ascending
     unsigned mask[kSharedScanCap]; // bit i: within the list radius of tile atom i
     double tx[kTileCap], ty[kTileCap], tz[kTileCap];
-    int ta[kTileCap];
+    int ta[kTileCap], tm[kTileCap];  // tile atoms and their molecules
+    int wcnt[kScanRoundsMax][16];    // kept atoms per (round, wave)
 };
 
 // Number of kept atoms, or -1 (nothing kept, workgroup-uniform) when the
-// tile spans molecules, the molecule has a cell grid or more than
-// kSharedScanCap atoms.  All threads of the workgroup call it.
+// tile has no shared-scan molecule m (S.tile_mol) or its atoms turn out not
+// to match it.  All threads of the workgroup call it.  The tile's molecule
+// comes from the host's table, so the molecule's ranges and the candidates'
+// positions are requested without waiting for the tile atoms' molecules,
+// which are only checked; three barriers in all.
 template <int NT>
-__device__ __forceinline__ int shared_scan(const Sys& S, const int* atoms, int cnt, SharedScan& sc, int* wcnt,
-                                           int tid)
+__device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms, int cnt, SharedScan& sc, int tid)
 {
-    const int m = S.mol[atoms[0]];
-    if (S.molgrid[m] >= 0) return -1;
-    for (int i = 1; i < cnt; ++i)
-        if (S.mol[atoms[i]] != m) return -1;
+    static_assert(NT == 1024 && kScanRoundsMax * NT >= kSharedScanCap, "one candidate per thread and round");
+    if (m < 0) return -1;
     int2 rg[kNumSpecies];
     int cum[kNumSpecies + 1];
     cum[0] = 0;
@@ -213,8 +214,25 @@ __device__ __forceinline__ int shared_scan(const Sys& S, const int* atoms, int c
         rg[e] = S.mrange[m * kNumSpecies + e];
         cum[e + 1] = cum[e] + (rg[e].y - rg[e].x);
     }
-    const int total = cum[kNumSpecies];
-    if (total > kSharedScanCap) return -1;
+    const bool nogrid = S.molgrid[m] < 0;
+    const int total = min(cum[kNumSpecies], kSharedScanCap);
+    // every position this thread tests is requested before any is tested
+    double4 pc[kScanRoundsMax];
+    int cc[kScanRoundsMax];
+#pragma unroll
+    for (int r = 0; r < kScanRoundsMax; ++r) {
+        const int q = r * NT + tid;
+        cc[r] = -1;
+        pc[r] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (q < total) {
+            int c = 0;
+#pragma unroll
+            for (int e = 0; e < kNumSpecies; ++e)
+                if (q >= cum[e] && q < cum[e + 1]) c = rg[e].x + (q - cum[e]);
+            cc[r] = c;
+            pc[r] = S.pos[c];
+        }
+    }
     if (tid < cnt) {
         const int a = atoms[tid];
         const double4 p = S.pos[a];
@@ -222,39 +240,43 @@ __device__ __forceinline__ int shared_scan(const Sys& S, const int* atoms, int c
         sc.ty[tid] = p.y;
         sc.tz[tid] = p.z;
         sc.ta[tid] = a;
+        sc.tm[tid] = S.mol[a];
     }
     __syncthreads();
+    bool ok = nogrid && cum[kNumSpecies] <= kSharedScanCap;
+    for (int i = 0; i < cnt; ++i) ok = ok && sc.tm[i] == m;
+    if (!ok) return -1;  // workgroup-uniform
     const int wave = tid >> 6;
-    int nl = 0;
-    for (int q0 = 0; q0 < total; q0 += NT) {
-        const int q = q0 + tid;
-        unsigned mk = 0;
-        int c = 0;
-        if (q < total) {
+    unsigned mk[kScanRoundsMax];
+    unsigned long long bal[kScanRoundsMax];
 #pragma unroll
-            for (int e = 0; e < kNumSpecies; ++e)
-                if (q >= cum[e] && q < cum[e + 1]) c = rg[e].x + (q - cum[e]);
-            const double4 pc = S.pos[c];
+    for (int r = 0; r < kScanRoundsMax; ++r) {
+        mk[r] = 0;
+        if (cc[r] >= 0)
             for (int i = 0; i < cnt; ++i)
-                if (c != sc.ta[i] && in_pair_list(S, pc.x - sc.tx[i], pc.y - sc.ty[i], pc.z - sc.tz[i]))
-                    mk |= 1u << i;
-        }
-        const unsigned long long bal = __ballot(mk != 0);
-        if ((tid & 63) == 0) wcnt[wave] = __popcll(bal);
-        __syncthreads();
+                if (cc[r] != sc.ta[i] &&
+                    in_pair_list(S, pc[r].x - sc.tx[i], pc[r].y - sc.ty[i], pc[r].z - sc.tz[i]))
+                    mk[r] |= 1u << i;
+        bal[r] = __ballot(mk[r] != 0);
+        if ((tid & 63) == 0) sc.wcnt[r][wave] = __popcll(bal[r]);
+    }
+    __syncthreads();
+    int nl = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRoundsMax; ++r) {
         int off = nl, tot = 0;
         for (int w = 0; w < NT / 64; ++w) {
-            if (w < wave) off += wcnt[w];
-            tot += wcnt[w];
+            if (w < wave) off += sc.wcnt[r][w];
+            tot += sc.wcnt[r][w];
         }
-        if (mk != 0) {
-            const int slot = off + lanes_below(bal);
-            sc.idx[slot] = c;
-            sc.mask[slot] = mk;
+        if (mk[r] != 0) {
+            const int slot = off + lanes_below(bal[r]);
+            sc.idx[slot] = cc[r];
+            sc.mask[slot] = mk[r];
         }
         nl += tot;
-        __syncthreads();  // wcnt is rewritten by the next chunk
     }
+    __syncthreads();
     return nl;
 }
 

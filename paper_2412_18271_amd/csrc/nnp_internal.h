@@ -45,6 +45,7 @@ constexpr int kCapMax = 256;  // largest pair-list capacity (slot fits in 8 bits
 constexpr int kRing = 4096;   // energy log ring (steps)
 constexpr int kXcds = 8;      // accelerator complex dies; workgroups go round-robin
 constexpr int kTileCap = 16;  // largest atoms-per-tile (MFMA columns)
+constexpr int kSharedScanCap = 4096;  // molecule size up to which a tile's pair lists are rebuilt together
 constexpr int kFaccCopies = 4;  // copies of the force sums: workgroup b adds into copy (b / 8) mod 4
 
 // Per-element FP32 weight block (floats).  Forward dense layers read the
@@ -132,6 +133,8 @@ struct Sys {
     const int2* mrange;  // [nmol * 4] internal index range of each element of a molecule
     const int4* tiles;      // {first atom of the initial tiling, count, element, 0}
     const int* tile_atoms;  // [ntiles][kTileCap] atom in each column of a tile
+    const int* tile_mol;    // [ntiles] the molecule of all of a tile's atoms when it is scanned without a
+                            // cell grid and has at most kSharedScanCap atoms, else -1
     int* work;              // [n] angular pairs + radial entries / 2 at the last evaluation
     int* nbr;
     int* ncnt;

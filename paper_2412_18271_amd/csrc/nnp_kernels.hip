@@ -191,7 +191,6 @@ struct PooledSmem {
         } adj;
     } u;
     float E[16];
-    int wcnt[16];  // per-wave counts of the shared candidate scan
 };
 
 // Workgroup of the pooled kernel: 16 waves for a tile of 10 atoms.  One wave
@@ -223,7 +222,9 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
                   sizeof(SharedScan) <= sizeof(sm.G) + sizeof(sm.Gx) && offsetof(Smem, G) % 16 == 0,
                   "candidate list over G and Gx");
     SharedScan& scan = *reinterpret_cast<SharedScan*>(sm.G);
-    const int nl = rb ? shared_scan<NT>(S, S.tile_atoms + blockIdx.x * kTileCap, tile.y, scan, sm.wcnt, tid) : -1;
+    const int nl = rb ? shared_scan<NT>(S, S.tile_mol[blockIdx.x], S.tile_atoms + blockIdx.x * kTileCap, tile.y,
+                                        scan, tid)
+                      : -1;
     if (act) {
         if (rb && S.molgrid[S.mol[a]] < 0) {
             if (nl >= 0) {
