@@ -3,7 +3,8 @@ the C ABI): lone atoms (no neighbours: the network of an all-zero
 descriptor, no force), dimers on both sides of the 3.5 A and 5.2 A cutoffs,
 collinear and right-angle trimers, a batch of molecules of one, two and
 three atoms next to larger ones (ragged tiles, tiles mixing molecules), and
-capacity overflow reported as an error.
+capacity overflow reported as an error, and invalid positions (NaN, Inf,
+coincident atoms) rejected before any device work.
 """
 
 import sys
@@ -141,3 +142,48 @@ def test_capacity_overflow_is_an_error(weights, T):
     _say("overflow:", ei.value)
     assert "capacity exceeded" in str(ei.value)
     ctx.close()
+
+
+@pytest.mark.parametrize("path", ["fused", "plain"])
+def test_invalid_positions_are_rejected_and_context_recovers(weights, path):
+    """NaN or infinite coordinates and two atoms at one point are rejected on
+    the host before any device work (status NNP_ERR_NONFINITE = 2), both as
+    the first positions a context sees and later, by compute and by
+    set_state; valid positions then give the same result as before."""
+    import paper_2412_18271_amd as P
+    s = synth.make_config("mol22")
+
+    def broken():
+        for kind in ("nan", "inf", "coincident"):
+            p = s.pos.copy()
+            if kind == "nan":
+                p[7, 1] = np.nan
+            elif kind == "inf":
+                p[3, 2] = -np.inf
+            else:
+                p[11] = p[4]
+            yield kind, p
+
+    fresh = P.Context.from_system(s, dtype="fp32", path=path)
+    for kind, p in broken():
+        with pytest.raises(P.NNPError) as ei:
+            fresh.compute(p)
+        assert ei.value.status == 2, (kind, ei.value)
+    E0, F0 = fresh.compute(s.pos)
+    Eo, Eio, Fo = oracle.energy_forces(s.pos, s.species, s.weights)
+    assert np.abs(F0 - Fo).max() <= TOL_F["fp32"]
+    for kind, p in broken():
+        with pytest.raises(P.NNPError) as ei:
+            fresh.compute(p)
+        assert ei.value.status == 2, (kind, ei.value)
+        with pytest.raises(P.NNPError) as ei:
+            fresh.set_state(p, s.vel)
+        assert ei.value.status == 2, (kind, ei.value)
+        _say("%s positions rejected (%s path): %s" % (kind, path, ei.value))
+    E1, F1 = fresh.compute(s.pos)
+    assert E1[0] == E0[0] and np.array_equal(F1, F0)
+    fresh.set_state(s.pos, s.vel)
+    fresh.step(0.5, 5)
+    x, _, _, _ = oracle.vv(s.pos, s.vel, s.masses, s.species, s.weights, 0.5, 5)
+    assert np.abs(fresh.get_state()["pos"] - x).max() <= 1e-5
+    fresh.close()
