@@ -76,9 +76,12 @@ def test_traffic_summary_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
     only while the kernel sources hash as recorded."""
     txt = open(bench.TRAFFIC_SUMMARY).read()
     kv = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
+    current = tmp_path / "current.md"
+    current.write_text(txt.replace(kv["kernel_source_sha256"], bench.kernel_source_hash()))
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(current))
     assert bench.load_traffic(kv["variant"]) == int(kv["hbm_bytes_per_launch"])
     assert bench.load_traffic("fp32:plain") is None
-    stale = tmp_path / "t.md"
+    stale = tmp_path / "stale.md"
     stale.write_text(txt.replace(kv["kernel_source_sha256"], "0" * 64))
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(stale))
     assert bench.load_traffic(kv["variant"]) is None
