@@ -815,41 +815,70 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
     const double4 pa = S.pos[a];
     const int cx = cell_coord(pa.x, G.ox, G.ihx, G.nx, G.periodic), cy = cell_coord(pa.y, G.oy, G.ihy, G.ny, G.periodic),
               cz = cell_coord(pa.z, G.oz, G.ihz, G.nz, G.periodic);
+    // lane q < 27 takes neighbour cell q (dz, dy, dx = q / 9, q / 3 mod 3,
+    // q mod 3, each minus 1) and reads its atom range; a scan of the range
+    // lengths over the lanes lays the cells end to end as one candidate
+    // sequence, read kScanUnroll chunks of 64 at a time.  The candidates'
+    // order does not matter: the list is sorted below.  Periodic grids have
+    // at least 3 cells per dimension, so the 27 wrapped cells are distinct.
+    int cb = 0, len = 0;
+    if (lane < 27) {
+        int z = cz + lane / 9 - 1, y = cy + (lane / 3) % 3 - 1, x = cx + lane % 3 - 1;
+        if (G.periodic) {
+            z = z < 0 ? z + G.nz : (z >= G.nz ? z - G.nz : z);
+            y = y < 0 ? y + G.ny : (y >= G.ny ? y - G.ny : y);
+            x = x < 0 ? x + G.nx : (x >= G.nx ? x - G.nx : x);
+        }
+        if (x >= 0 && x < G.nx && y >= 0 && y < G.ny && z >= 0 && z < G.nz) {
+            const int c = G.first + (z * G.ny + y) * G.nx + x;
+            cb = S.cell_start[c];
+            len = S.cell_start[c + 1] - cb;
+        }
+    }
+    int incl = len;  // over lanes 0..31 (lanes 27..31 add nothing)
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, 26);
     int count = 0;
-    // periodic grids have >= 3 cells per dimension, so the 27 wrapped cells are distinct
-    for (int dz = -1; dz <= 1; ++dz) {
-        int z = cz + dz;
-        if (G.periodic) z = z < 0 ? z + G.nz : (z >= G.nz ? z - G.nz : z);
-        if (z < 0 || z >= G.nz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            int y = cy + dy;
-            if (G.periodic) y = y < 0 ? y + G.ny : (y >= G.ny ? y - G.ny : y);
-            if (y < 0 || y >= G.ny) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                int x = cx + dx;
-                if (G.periodic) x = x < 0 ? x + G.nx : (x >= G.nx ? x - G.nx : x);
-                if (x < 0 || x >= G.nx) continue;
-                const int c = G.first + (z * G.ny + y) * G.nx + x;
-                const int b0 = S.cell_start[c], b1 = S.cell_start[c + 1];
-                for (int i0 = b0; i0 < b1; i0 += 64) {
-                    const int i = i0 + lane;
-                    bool ok = false;
-                    int b = -1;
-                    if (i < b1) {
-                        b = S.cell_atoms[i];
-                        if (b != a) {
-                            const double4 pb = S.pos[b];
-                            double ex = pb.x - pa.x, ey = pb.y - pa.y, ez = pb.z - pa.z;
-                            min_image(S, ex, ey, ez);
-                            ok = ex * ex + ey * ey + ez * ez < (double)S.rlist2;
-                        }
-                    }
-                    const unsigned long long mk = __ballot(ok);
-                    const int slot = count + lanes_below(mk);
-                    if (ok && slot < kCapMax) K[slot] = b;
-                    count += __popcll(mk);
-                }
+    for (int f0 = 0; f0 < total; f0 += 64 * kScanUnroll) {
+        int bq[kScanUnroll];
+        double4 pb[kScanUnroll];
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) {
+            const int f = f0 + 64 * u + lane;
+            const int fc = f < total ? f : 0;
+            // q = the cell holding fc: the number of cells whose inclusive
+            // end is <= fc (ends are non-decreasing over lanes 0..31, and
+            // every lane takes part in the shuffles)
+            int q = 0;
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1)
+                if (__shfl(incl, q + step - 1) <= fc) q += step;
+            const int start = __shfl(cb, q), first = __shfl(excl, q);
+            bq[u] = f < total ? S.cell_atoms[start + (fc - first)] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) {
+            pb[u] = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (bq[u] >= 0 && bq[u] != a) pb[u] = S.pos[bq[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) {
+            if (f0 + 64 * u >= total) break;  // wave-uniform
+            bool ok = false;
+            if (bq[u] >= 0 && bq[u] != a) {
+                double ex = pb[u].x - pa.x, ey = pb[u].y - pa.y, ez = pb[u].z - pa.z;
+                min_image(S, ex, ey, ez);
+                ok = ex * ex + ey * ey + ez * ez < (double)S.rlist2;
             }
+            const unsigned long long mk = __ballot(ok);
+            const int slot = count + lanes_below(mk);
+            if (ok && slot < kCapMax) K[slot] = bq[u];
+            count += __popcll(mk);
         }
     }
     const int kept = count < kCapMax ? count : kCapMax;
