@@ -19,10 +19,14 @@ The headline value is the fastest variant whose max force error against the
 FP64 oracle is <= 1e-2 eV/A on the initial configuration and on 10 snapshots
 of a trajectory (the rerun check).
 
-Per variant the timed region is K graph-replayed steps after W warm-up steps;
-the same K steps are then replayed from the same state without a graph, with
-HIP events on the context stream around every kernel launch, which gives the
-average duration of the evaluation kernel for the roofline report.
+Per variant the timed region is K graph-replayed steps after W warm-up steps,
+repeated REPEATS times from the same initial state; value is the median and
+the spread (max - min) / median is reported.  The graphs of every block
+length the timed steps use are captured and instantiated before the timed
+region (nnp_capture), so it replays cached graphs only.  The same K steps
+are then replayed from the same state without a graph, with HIP events on
+the context stream around every kernel launch, which gives the average
+duration of the evaluation kernel for the roofline report.
 
 Other modes (not part of the default run): --precision (errors per network
 dtype on a second 2,500-atom cluster and on 23,000 atoms, and NVE drift),
@@ -50,6 +54,7 @@ sys.path.insert(0, ROOT)
 
 DT_FS = 0.5
 F_TOL = 1e-2
+REPEATS = 5
 N_SNAPSHOTS = 10
 VARIANTS = (("fp32", "plain"), ("fp32", "fused"), ("bf16", "fused"), ("bf16x3", "fused"), ("fp8", "fused"))
 KERNEL_MODE = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp8": 3}  # template MODE of the evaluation kernels
@@ -137,27 +142,52 @@ def event_timed(ctx, s, warmup, steps):
             "radial_pairs": rad / steps, "angular_triples": tri / steps}
 
 
-def run_variant(P, s, dtype, path, steps, warmup, refs):
+def timed_steps(ctx, s, steps, warmup, repeats=REPEATS):
+    """Seconds of `steps` graph-replayed MD steps after `warmup` untimed
+    ones, `repeats` times from the same initial state.  The graphs of the
+    timed block lengths are captured before the clock starts."""
+    out = []
+    for _ in range(repeats):
+        ctx.set_state(s.pos, s.vel)
+        ctx.step(DT_FS, warmup, graph=True)
+        ctx.capture(DT_FS, steps)
+        ctx.stats()  # synchronises
+        t0 = time.perf_counter()
+        ctx.step(DT_FS, steps, graph=True)
+        st = ctx.stats()
+        out.append(time.perf_counter() - t0)
+    return out, st
+
+
+def rate_summary(seconds, steps, units=1):
+    """Median rate over the repeats and its spread."""
+    rates = [units * steps / x for x in seconds]
+    med = float(np.median(rates))
+    return {"rate": med, "ms_per_step": 1e3 * float(np.median(seconds)) / steps,
+            "repeats": rates, "spread": (max(rates) - min(rates)) / med}
+
+
+def run_variant(P, s, dtype, path, steps, warmup, refs, tune=None):
     ctx = P.Context.from_system(s, dtype=dtype, path=path)
     try:
         errs = []
         for pos, F_ref in refs:
             _, F = ctx.compute(pos)
             errs.append(float(np.abs(F - F_ref).max()))
-        ctx.set_state(s.pos, s.vel)
-        ctx.step(DT_FS, warmup, graph=True)
-        ctx.stats()  # synchronises
-        t0 = time.perf_counter()
-        ctx.step(DT_FS, steps, graph=True)
-        st = ctx.stats()
-        t1 = time.perf_counter()
+        tuned = None
+        if tune is not None:
+            ctx.set_state(s.pos, s.vel)
+            tuned = ctx.autotune(tune)
+        secs, st = timed_steps(ctx, s, steps, warmup)
+        rs = rate_summary(secs, steps)
         U, K = ctx.energy_log(min(steps + 1, 4096))
         dH, slope = drift(U[:, 0], K[:, 0], s.n_atoms)
         final_finite = bool(np.isfinite(ctx.get_state()["pos"]).all())
         kt = event_timed(ctx, s, warmup, steps)
         return {
-            "dtype": dtype, "path": path, "steps_per_s": steps / (t1 - t0),
-            "ms_per_step": 1e3 * (t1 - t0) / steps, "max_force_err": errs[0],
+            "dtype": dtype, "path": path, "steps_per_s": rs["rate"],
+            "ms_per_step": rs["ms_per_step"], "repeats_steps_per_s": rs["repeats"], "spread": rs["spread"],
+            "autotune": tuned, "max_force_err": errs[0],
             "max_force_err_snapshots": max(errs[1:]) if len(errs) > 1 else None,
             "drift_max_abs_eV": dH, "drift_slope_meV_per_atom_ps": slope,
             "rebuilds": st["rebuilds"], "forced_rebuilds": st["forced_rebuilds"],
@@ -174,18 +204,13 @@ def langevin_leg(P, s, dtype, path, steps, warmup):
     friction of 0.1 ps^-1, same graph-replayed blocks as the NVE run."""
     ctx = P.Context.from_system(s, dtype=dtype, path=path)
     try:
-        ctx.set_state(s.pos, s.vel)
         ctx.set_thermostat(300.0, 0.1, 0)
-        ctx.step(DT_FS, warmup, graph=True)
-        ctx.stats()
-        t0 = time.perf_counter()
-        ctx.step(DT_FS, steps, graph=True)
-        ctx.stats()
-        t1 = time.perf_counter()
+        secs, _ = timed_steps(ctx, s, steps, warmup)
+        rs = rate_summary(secs, steps)
         _, K = ctx.energy_log(min(steps, 4096))
         return {"dtype": dtype, "path": path, "temperature_K": 300.0, "friction_per_ps": 0.1,
-                "steps_per_s": steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
-                "ns_per_day": steps / (t1 - t0) * DT_FS * 86400 / 1e6,
+                "steps_per_s": rs["rate"], "ms_per_step": rs["ms_per_step"], "spread": rs["spread"],
+                "ns_per_day": rs["rate"] * DT_FS * 86400 / 1e6,
                 "kinetic_temperature_K": float(2.0 * K[:, 0].mean() / (3 * s.n_atoms * 8.617333262e-5))}
     finally:
         ctx.close()
@@ -202,15 +227,10 @@ def periodic_leg(P, dtype, path, steps, warmup):
     ctx = P.Context.from_system(s, dtype=dtype, path=path)
     try:
         _, F = ctx.compute(s.pos)
-        ctx.set_state(s.pos, s.vel)
-        ctx.step(DT_FS, warmup, graph=True)
-        ctx.stats()
-        t0 = time.perf_counter()
-        ctx.step(DT_FS, steps, graph=True)
-        st = ctx.stats()
-        t1 = time.perf_counter()
+        secs, st = timed_steps(ctx, s, steps, warmup)
+        rs = rate_summary(secs, steps)
         return {"workload": "box2500: 2,500 atoms, periodic cube L = %.2f A" % s.box[0], "dtype": dtype,
-                "path": path, "steps_per_s": steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+                "path": path, "steps_per_s": rs["rate"], "ms_per_step": rs["ms_per_step"], "spread": rs["spread"],
                 "max_force_err": float(np.abs(F - F_ref).max()), "rebuilds": st["rebuilds"]}
     finally:
         ctx.close()
@@ -226,13 +246,10 @@ def batch_leg(P, steps, warmup):
     out = {"n_molecules": M, "n_atoms": int(s.n_atoms), "steps": steps, "dtype": "bf16x3"}
     ctx = P.Context.from_system(s, dtype="bf16x3", path="fused")
     try:
-        ctx.set_state(s.pos, s.vel)
-        ctx.step(DT_FS, warmup, graph=True)
-        ctx.stats()
-        t0 = time.perf_counter()
-        ctx.step(DT_FS, steps, graph=True)
-        ctx.stats()
-        out["batched_molecule_steps_per_s"] = M * steps / (time.perf_counter() - t0)
+        secs, _ = timed_steps(ctx, s, steps, warmup)
+        rs = rate_summary(secs, steps, M)
+        out["batched_molecule_steps_per_s"] = rs["rate"]
+        out["batched_spread"] = rs["spread"]
     finally:
         ctx.close()
     ctxs = []
@@ -246,6 +263,8 @@ def batch_leg(P, steps, warmup):
                            (False, "per_molecule_eager_molecule_steps_per_s")):
             for c in ctxs:
                 c.step(DT_FS, warmup, graph=graph)
+                if graph:
+                    c.capture(DT_FS, steps)
             for c in ctxs:
                 c.stats()
             t0 = time.perf_counter()
@@ -606,13 +625,16 @@ def main():
         "radial_pairs_per_launch": rad, "angular_triples_per_launch": tri,
         "mlp_tflops": mlp_flop / t_eval / 1e12, "mlp_peak_tflops": mlp_peak,
         "mlp_frac": mlp_flop / t_eval / 1e12 / mlp_peak,
-        "speed_of_light_us": sol_s * 1e6, "speed_of_light_frac": sol_s / t_eval,
+        # time at peak of both halves (descriptor VALU work at the FP32 vector
+        # peak + network work at its dtype's peak) over the kernel's time
+        "combined_frac": sol_s / t_eval, "speed_of_light_us": sol_s * 1e6,
         "hbm_gbs_from_traffic": None if traffic is None else traffic / t_eval / 1e9,
     }
     out = {
         "metric": "NNP energy+force evals/s & ns/day (2.5k atoms), BF16-MFMA vs FP32 plain",
         "value": best["steps_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+        "repeats": REPEATS, "repeats_value": best["repeats_steps_per_s"], "spread": best["spread"],
         "scaling": "weak", "vs_baseline": None, "dtype": best["dtype"], "data": "synthetic",
         "ns_per_day": best["steps_per_s"] * DT_FS * 86400 / 1e6,
         "config": {"workload": "cluster2500: 2,500-atom gas-phase cluster, NVE dt 0.5 fs, "

@@ -62,8 +62,18 @@ typedef enum {
                                 capacity overflow (neighbour list, LDS environment) */
 } nnp_status;
 
-/* What nnp_compute returns (the paper's Callable return flag: energy only,
- * forces then come from differentiation; or energy and explicit forces). */
+/* What nnp_compute and nnp_compute_device return (the paper's return flag of
+ * a registered Python callable, Methods section: the energy alone, the engine
+ * then obtaining the forces by differentiating it, or the energy together
+ * with explicit forces).
+ *   NNP_RETURN_ENERGY_FORCES  energy and forces (0 selects this);
+ *   NNP_RETURN_ENERGY         energy only: the evaluation runs the network
+ *                             forward alone (no input gradient, no adjoint),
+ *                             leaves the context's forces untouched, and a
+ *                             non-NULL forces argument is NNP_ERR_ARG.  Forces
+ *                             then come from differentiation: nnp_forces_device
+ *                             after nnp_energy_device, or the adjoint inside
+ *                             nnp_step (MD always needs them). */
 typedef enum { NNP_RETURN_ENERGY = 1, NNP_RETURN_ENERGY_FORCES = 3 } nnp_return;
 
 /* Arithmetic of the network GEMMs.  Descriptors and the adjoint are FP32 in
@@ -99,6 +109,7 @@ typedef struct {
     size_t weights_count;        /* number of floats in the blob (4 * 94689) */
     nnp_dtype mlp_dtype;
     nnp_path path;
+    nnp_return return_mode;      /* 0 or NNP_RETURN_ENERGY_FORCES, or NNP_RETURN_ENERGY */
     int32_t rebuild_every;       /* pair-list rebuild cadence in steps (e.g. 20), >= 1 */
     double skin;                 /* pair-list skin in A (e.g. 1.0), >= 0 */
     int32_t max_neighbors;       /* capacity of one atom's pair list (cutoff 5.2 + skin),
@@ -131,7 +142,11 @@ void nnp_destroy(nnp_context* ctx);
  *           one); else host [3] double, the edges of an orthorhombic periodic
  *           box, which becomes the context's box as with nnp_set_box;
  *   energy  host [n_molecules] double, molecule potential energies (eV);
- *   forces  host [n_atoms][3] double (eV/A), or NULL for energy only.
+ *   forces  host [n_atoms][3] double (eV/A), or NULL.  With return_mode
+ *           NNP_RETURN_ENERGY_FORCES the forces are computed either way (they
+ *           become the context's forces for a following nnp_step); with
+ *           NNP_RETURN_ENERGY only the energy is computed and forces must be
+ *           NULL (else NNP_ERR_ARG).
  * The positions become the context's current positions (velocities are kept);
  * the pair list is rebuilt.  Synchronises the context stream. */
 nnp_status nnp_compute(nnp_context* ctx, const double* pos, const double* box, double* energy,
@@ -142,7 +157,8 @@ nnp_status nnp_compute(nnp_context* ctx, const double* pos, const double* box, d
  *   d_pos     [n_atoms][3]; d_pos_is_f64 selects double (1) or float (0);
  *   d_energy  [n_molecules] double (written);
  *   d_forces  [n_atoms][3] double, or NULL for energy only (then the network
- *             backward and the adjoint are skipped).
+ *             backward and the adjoint are skipped); must be NULL with
+ *             return_mode NNP_RETURN_ENERGY (else NNP_ERR_ARG).
  * No host-side validation of the device positions is possible; a non-finite
  * result is reported by the next host-synchronising call. */
 nnp_status nnp_compute_device(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy,
@@ -198,6 +214,14 @@ nnp_status nnp_get_state(nnp_context* ctx, double* pos, double* vel, double* for
  * first use for the given block length and dt).  Returns after enqueueing;
  * nnp_get_state / nnp_energy_log synchronise. */
 nnp_status nnp_step(nnp_context* ctx, double dt_fs, int32_t n_steps, int32_t use_graph);
+
+/* Captures and instantiates the HIP graphs that nnp_step(ctx, dt_fs, n_steps,
+ * 1) replays (one per block length: min(n_steps, 100) and the remainder),
+ * without running any step, so that a following nnp_step with the same
+ * arguments replays cached graphs only (serving loops, timed regions).
+ * The state is unchanged.  NNP_ERR_STATE on the null stream or with extra
+ * force providers registered (their steps are not captured). */
+nnp_status nnp_capture(nnp_context* ctx, double dt_fs, int32_t n_steps);
 
 /* Extra force providers (the paper's callback mechanism, Methods: the engine
  * calls back into caller code for energies and forces; its explicit-force

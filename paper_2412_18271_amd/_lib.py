@@ -17,11 +17,12 @@ STATUS_NAMES = {0: "NNP_OK", 1: "NNP_ERR_ARG", 2: "NNP_ERR_NONFINITE", 3: "NNP_E
                 4: "NNP_ERR_OOM", 5: "NNP_ERR_HIP", 6: "NNP_ERR_STATE"}
 DTYPES = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
 PATHS = {"plain": 0, "fused": 1}
+RETURN_MODES = {"energy_forces": 3, "energy": 1}
 
 #: Every function the header declares.
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nnp_energy_device",
            "nnp_forces_device", "nnp_set_state",
-           "nnp_get_state", "nnp_step", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
+           "nnp_get_state", "nnp_step", "nnp_capture", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
            "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels", "nnp_time_steps",
            "nnp_set_thermostat", "nnp_set_box", "nnp_add_force", "nnp_clear_forces",
            "nnp_debug_fp8_encode",
@@ -44,6 +45,7 @@ class Params(ctypes.Structure):
         ("weights_count", ctypes.c_size_t),
         ("mlp_dtype", ctypes.c_int),
         ("path", ctypes.c_int),
+        ("return_mode", ctypes.c_int),
         ("rebuild_every", ctypes.c_int32),
         ("skin", ctypes.c_double),
         ("max_neighbors", ctypes.c_int32),
@@ -100,6 +102,7 @@ def load():
         "nnp_set_state": (st, [vp, P(d), P(d)]),
         "nnp_get_state": (st, [vp, P(d), P(d), P(d), P(d), P(d)]),
         "nnp_step": (st, [vp, d, i32, i32]),
+        "nnp_capture": (st, [vp, d, i32]),
         "nnp_energy_log": (st, [vp, i32, P(d), P(d), P(i32)]),
         "nnp_stats": (st, [vp, P(i64)]),
         "nnp_debug_descriptors": (st, [vp, P(d), P(ctypes.c_float)]),

@@ -20,12 +20,14 @@ class Context:
 
     species, masses, weights and mol_offsets are copied by the library at
     creation.  ``stream`` is a raw hipStream_t (int; 0 is the null stream)
-    or None for a stream the context owns.
+    or None for a stream the context owns.  ``return_mode`` is
+    "energy_forces" or "energy" (compute() then returns the energy only).
     """
 
     def __init__(self, species, masses, weights, mol_offsets=None, dtype: str = "fp32",
                  path: str = "fused", rebuild_every: int = 20, skin: float = 1.0,
-                 max_neighbors: int = 0, atoms_per_tile: int = 0, stream: Optional[int] = None):
+                 max_neighbors: int = 0, atoms_per_tile: int = 0, stream: Optional[int] = None,
+                 return_mode: str = "energy_forces"):
         self._lib = _lib.load()
         self._sp = np.ascontiguousarray(species, dtype=np.int32)
         self._m = np.ascontiguousarray(masses, dtype=np.float64)
@@ -39,6 +41,7 @@ class Context:
         self.n_molecules = int(self._off.shape[0] - 1)
         self.dtype = dtype
         self.path = path
+        self.return_mode = return_mode
         p = _lib.Params()
         p.n_atoms = n
         p.n_molecules = self.n_molecules
@@ -49,6 +52,7 @@ class Context:
         p.weights_count = int(self._w.shape[0])
         p.mlp_dtype = _lib.DTYPES[dtype]
         p.path = _lib.PATHS[path]
+        p.return_mode = _lib.RETURN_MODES[return_mode]
         p.rebuild_every = int(rebuild_every)
         p.skin = float(skin)
         p.max_neighbors = int(max_neighbors)
@@ -102,8 +106,11 @@ class Context:
         p = np.ascontiguousarray(pos, dtype=np.float64).reshape(self.n_atoms, 3)
         return p
 
-    def compute(self, pos, forces: bool = True, box=None):
-        """Energies per molecule (M,) and forces (N, 3) (None if not asked)."""
+    def compute(self, pos, forces: Optional[bool] = None, box=None):
+        """Energies per molecule (M,) and forces (N, 3) (None if not asked;
+        by default asked unless the context returns energy only)."""
+        if forces is None:
+            forces = self.return_mode != "energy"
         p = self._pos(pos)
         E = np.zeros(self.n_molecules, np.float64)
         F = np.zeros((self.n_atoms, 3), np.float64) if forces else None
@@ -141,6 +148,10 @@ class Context:
 
     def step(self, dt: float, n_steps: int, graph: bool = True):
         self._check(self._lib.nnp_step(self._h, float(dt), int(n_steps), 1 if graph else 0))
+
+    def capture(self, dt: float, n_steps: int):
+        """Captures the graphs step(dt, n_steps) replays, without stepping."""
+        self._check(self._lib.nnp_capture(self._h, float(dt), int(n_steps)))
 
     def add_force(self, fn, kind: str = "energy"):
         """Registers an extra force provider summed with the network (the

@@ -53,6 +53,7 @@ struct nnp_context {
     std::vector<int> molgrid;  // grid of each molecule, -1: scanned without a cell grid
     nnp_dtype dtype = NNP_MLP_FP32;
     nnp_path path = NNP_PATH_FUSED;
+    bool energy_only = false;  // return_mode NNP_RETURN_ENERGY
     int rebuild_every = 20;
     double skin = 1.0;
     hipStream_t stream = nullptr;
@@ -689,13 +690,16 @@ nnp_status apply_extra(nnp_context* c)
     return NNP_OK;
 }
 
-// One complete evaluation: network forces, extra providers, force gather.
-nnp_status full_compute(nnp_context* c)
+// One complete evaluation: network energies (and forces when grad), extra
+// providers, force gather.  Without grad the network's forward runs alone
+// and the gather leaves the context's forces untouched (it still empties the
+// fixed-point sums that the providers may have filled).
+nnp_status full_compute(nnp_context* c, bool grad = true)
 {
-    HIP_TRY(c, enqueue_eval(c, true));
+    HIP_TRY(c, enqueue_eval(c, grad));
     const nnp_status xs = apply_extra(c);
     if (xs != NNP_OK) return xs;
-    HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
+    HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream, grad));
     return NNP_OK;
 }
 
@@ -722,6 +726,32 @@ hipError_t enqueue_steps(nnp_context* c, double dt, int nsteps, bool first_kick)
         if (e == hipSuccess) e = launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream);
     }
     return e;
+}
+
+// Steps per captured block of nnp_step.
+constexpr int kGraphBlock = 100;
+
+// The executable graph of one block of len steps (captured and instantiated
+// on first use, then cached by everything its kernel arguments depend on).
+nnp_status block_graph(nnp_context* c, double dt, int len, hipGraphExec_t* out)
+{
+    const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T, c->S.gamma, c->S.kT, c->S.seed);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        hipGraph_t g;
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_steps(c, dt, len, true);
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess) return hip_fail(c, e, "capture");
+        if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+        hipGraphExec_t x;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        it = c->graphs.emplace(key, x).first;
+    }
+    *out = it->second;
+    return NNP_OK;
 }
 
 nnp_status check_device_flags(nnp_context* c)
@@ -772,6 +802,16 @@ const char* nnp_status_string(nnp_status s)
 
 const char* nnp_last_error(const nnp_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+// An enum field of the caller's struct as the integer it holds: a C caller
+// may store any int there, and reading a value outside the enumerators
+// through the C++ enum type is undefined.
+static int enum_raw(const void* field)
+{
+    int v;
+    std::memcpy(&v, field, sizeof v);
+    return v;
+}
+
 static nnp_status validate_params(const nnp_params* p, std::string& msg)
 {
     if (!p) return msg = "params is NULL", NNP_ERR_ARG;
@@ -792,10 +832,15 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
     if (p->weights_count != 4 * kBlobPerElement) return msg = "weights_count must be 4 * 94689", NNP_ERR_ARG;
     for (size_t i = 0; i < p->weights_count; ++i)
         if (!std::isfinite(p->weights[i])) return msg = "non-finite weight", NNP_ERR_NONFINITE;
-    if (p->mlp_dtype != NNP_MLP_FP32 && p->mlp_dtype != NNP_MLP_BF16 && p->mlp_dtype != NNP_MLP_BF16_SPLIT &&
-        p->mlp_dtype != NNP_MLP_FP8)
+    static_assert(sizeof(nnp_dtype) == sizeof(int) && sizeof(nnp_path) == sizeof(int) &&
+                      sizeof(nnp_return) == sizeof(int),
+                  "enum fields are int-sized");
+    const int dt = enum_raw(&p->mlp_dtype), pa = enum_raw(&p->path), rm = enum_raw(&p->return_mode);
+    if (dt != NNP_MLP_FP32 && dt != NNP_MLP_BF16 && dt != NNP_MLP_BF16_SPLIT && dt != NNP_MLP_FP8)
         return msg = "unknown mlp_dtype", NNP_ERR_ARG;
-    if (p->path != NNP_PATH_PLAIN && p->path != NNP_PATH_FUSED) return msg = "unknown path", NNP_ERR_ARG;
+    if (pa != NNP_PATH_PLAIN && pa != NNP_PATH_FUSED) return msg = "unknown path", NNP_ERR_ARG;
+    if (rm != 0 && rm != NNP_RETURN_ENERGY && rm != NNP_RETURN_ENERGY_FORCES)
+        return msg = "unknown return_mode", NNP_ERR_ARG;
     if (p->rebuild_every < 1) return msg = "rebuild_every must be >= 1", NNP_ERR_ARG;
     if (!(p->skin >= 0.0) || !std::isfinite(p->skin) || p->skin > 5.0) return msg = "skin must be in [0, 5] A", NNP_ERR_ARG;
     if (p->max_neighbors < 0 || p->max_neighbors > kCapMax) return msg = "max_neighbors must be in [0, 256]", NNP_ERR_ARG;
@@ -825,6 +870,7 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     c->T_auto = p->atoms_per_tile == 0 && p->path == NNP_PATH_FUSED;
     c->dtype = p->mlp_dtype;
     c->path = p->path;
+    c->energy_only = p->return_mode == NNP_RETURN_ENERGY;
     c->rebuild_every = p->rebuild_every;
     c->skin = p->skin;
     c->species.assign(p->species, p->species + c->n);
@@ -1078,10 +1124,12 @@ nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, dou
         if (bs != NNP_OK) return bs;
     }
     if (!pos || !energy) return fail(c, NNP_ERR_ARG, "pos and energy are required");
+    if (forces && c->energy_only) return fail(c, NNP_ERR_ARG, "the context returns energy only: forces must be NULL");
     nnp_status s = upload_positions(c, pos);
     if (s != NNP_OK) return s;
     HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
-    s = full_compute(c);
+    const bool grad = !c->energy_only;
+    s = full_compute(c, grad);
     if (s != NNP_OK) return s;
     std::vector<double4> f4;
     if (forces) {
@@ -1099,7 +1147,7 @@ nnp_status nnp_compute(nnp_context* c, const double* pos, const double* box, dou
             forces[3 * i + 1] = f4[k].y;
             forces[3 * i + 2] = f4[k].z;
         }
-    c->forces_current = true;
+    c->forces_current = grad;
     c->kick_pending = false;
     c->err.clear();
     return NNP_OK;
@@ -1111,17 +1159,14 @@ nnp_status nnp_compute_device(nnp_context* c, const void* d_pos, int is_f64, dou
     c->diff_state = 0;
     if (!d_pos || !d_energy) return fail(c, NNP_ERR_ARG, "d_pos and d_energy are required");
     if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions once with nnp_set_state or nnp_compute first");
+    if (d_forces && c->energy_only)
+        return fail(c, NNP_ERR_ARG, "the context returns energy only: d_forces must be NULL");
     HIP_TRY(c, launch_positions_in(c->S, d_pos, is_f64 ? 1 : 0, c->stream));
     HIP_TRY(c, launch_invalidate_lists(c->S, c->stream));
     const bool grad = d_forces != nullptr;
-    if (grad) {
-        const nnp_status fs = full_compute(c);
-        if (fs != NNP_OK) return fs;
-        HIP_TRY(c, launch_forces_out(c->S, d_forces, c->stream));
-    } else {
-        HIP_TRY(c, enqueue_eval(c, false));
-        HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
-    }
+    const nnp_status fs = full_compute(c, grad);
+    if (fs != NNP_OK) return fs;
+    if (grad) HIP_TRY(c, launch_forces_out(c->S, d_forces, c->stream));
     HIP_TRY(c, launch_energy_out(c->S, d_energy, c->stream));
     c->forces_current = grad;
     c->kick_pending = false;
@@ -1141,7 +1186,7 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         if (fs != NNP_OK) return fs;
         c->forces_current = true;
     }
-    const int B = std::min<int>(nsteps, 100);
+    const int B = std::min<int>(nsteps, kGraphBlock);
     if (!c->extra.empty()) {
         for (int left = nsteps; left > 0; left -= B) {
             nnp_status bs = rebalance_tiles(c);
@@ -1163,22 +1208,10 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
         return NNP_OK;
     }
     auto run_block = [&](int len) -> nnp_status {
-        const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T, c->S.gamma, c->S.kT, c->S.seed);
-        auto it = c->graphs.find(key);
-        if (it == c->graphs.end()) {
-            hipGraph_t g;
-            HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_steps(c, dt, len, true);
-            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-            if (e != hipSuccess) return hip_fail(c, e, "capture");
-            if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
-            hipGraphExec_t x;
-            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-            it = c->graphs.emplace(key, x).first;
-        }
-        HIP_TRY(c, hipGraphLaunch(it->second, c->stream));
+        hipGraphExec_t x = nullptr;
+        const nnp_status gs = block_graph(c, dt, len, &x);
+        if (gs != NNP_OK) return gs;
+        HIP_TRY(c, hipGraphLaunch(x, c->stream));
         return NNP_OK;
     };
     int left = nsteps;
@@ -1192,6 +1225,22 @@ nnp_status nnp_step(nnp_context* c, double dt, int32_t nsteps, int32_t use_graph
     }
     c->kick_pending = true;
     return NNP_OK;
+}
+
+nnp_status nnp_capture(nnp_context* c, double dt, int32_t nsteps)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, NNP_ERR_ARG, "dt must be finite and > 0");
+    if (nsteps < 0) return fail(c, NNP_ERR_ARG, "n_steps must be >= 0");
+    if (c->stream == nullptr) return fail(c, NNP_ERR_STATE, "graphs cannot be captured on the null stream");
+    if (!c->extra.empty()) return fail(c, NNP_ERR_STATE, "steps with extra force providers are not captured");
+    if (nsteps == 0) return NNP_OK;
+    const int B = std::min<int>(nsteps, kGraphBlock);
+    hipGraphExec_t x = nullptr;
+    nnp_status s = block_graph(c, dt, B, &x);
+    if (s == NNP_OK && nsteps % B != 0) s = block_graph(c, dt, nsteps % B, &x);
+    if (s == NNP_OK) c->err.clear();
+    return s;
 }
 
 nnp_status nnp_add_force(nnp_context* c, nnp_force_fn fn, void* user, double* d_pos, double* d_forces,

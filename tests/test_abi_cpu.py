@@ -70,6 +70,7 @@ def _params(P, s, **kw):
     ("weights_count", 10, 1),
     ("mlp_dtype", 7, 1),
     ("path", 5, 1),
+    ("return_mode", 2, 1),
     ("rebuild_every", 0, 1),
     ("skin", -1.0, 1),
     ("max_neighbors", 300, 1),
@@ -117,6 +118,7 @@ def test_null_context_calls_fail_cleanly():
     lib = P.load()
     assert lib.nnp_compute(None, None, None, None, None) == 1
     assert lib.nnp_step(None, 0.5, 1, 0) == 1
+    assert lib.nnp_capture(None, 0.5, 1) == 1
     assert lib.nnp_set_state(None, None, None) == 1
     lib.nnp_destroy(None)
 

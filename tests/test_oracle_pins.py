@@ -503,3 +503,23 @@ def test_two_force_providers_add(make_system):
         _, _, U, K = oracle.vv(x, s.vel, s.masses, s.species, s.weights, dt, steps, model=3)
         amp.append(np.max(np.abs(U + K - U[0] - K[0])))
     assert 3.0 < amp[0] / amp[1] < 5.0
+
+
+def test_periodic_vv_large_box_equals_gas_phase_vv(make_system):
+    """The periodic velocity-Verlet loop in a box far wider than the 10.4 A
+    reach (the molecule straddling a face, so that wrapping moves atoms
+    across it) follows the gas-phase velocity Verlet of the C oracle, which
+    the harmonic closed form pins: positions, velocities, potential and
+    kinetic energy at every step.  A wrong kick order, a missing half kick or
+    a wrong kinetic-energy unit breaks it."""
+    s = make_system("mol22")
+    pos = s.pos + np.array([-5.0, 37.0, 100.0])
+    box = [60.0, 61.0, 62.0]
+    x, v, U, K = oracle.periodic_vv(pos, s.vel, s.masses, s.species, s.weights, box, 0.5, 12)
+    xg, vg, Ug, Kg = oracle.vv(pos, s.vel, s.masses, s.species, s.weights, 0.5, 12)
+    assert U.shape == Ug.shape == (13,) and K.shape == Kg.shape == (13,)
+    np.testing.assert_allclose(x, xg, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(v, vg, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(U, Ug, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(K, Kg, rtol=0, atol=1e-10)
+    assert np.abs(x - pos).max() > 1e-3  # the atoms did move
