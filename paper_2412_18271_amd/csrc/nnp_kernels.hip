@@ -393,22 +393,35 @@ __device__ __forceinline__ double3 langevin_noise(unsigned long long seed, int a
 __device__ __forceinline__ void drift_atom(const Sys& S, double dt, double ki, double3 z, double4& p, double4& v)
 {
     if (S.gamma > 0.0) {
-        p.x += 0.5 * dt * v.x;
-        p.y += 0.5 * dt * v.y;
-        p.z += 0.5 * dt * v.z;
+        const double hdt = 0.5 * dt;
+        p.x = fma(hdt, v.x, p.x);
+        p.y = fma(hdt, v.y, p.y);
+        p.z = fma(hdt, v.z, p.z);
         const double la = exp(-S.gamma * dt);
         const double sig = sqrt((1.0 - la * la) * S.kT * ki);
-        v.x = la * v.x + sig * z.x;
-        v.y = la * v.y + sig * z.y;
-        v.z = la * v.z + sig * z.z;
-        p.x += 0.5 * dt * v.x;
-        p.y += 0.5 * dt * v.y;
-        p.z += 0.5 * dt * v.z;
+        v.x = fma(la, v.x, sig * z.x);
+        v.y = fma(la, v.y, sig * z.y);
+        v.z = fma(la, v.z, sig * z.z);
+        p.x = fma(hdt, v.x, p.x);
+        p.y = fma(hdt, v.y, p.y);
+        p.z = fma(hdt, v.z, p.z);
     } else {
-        p.x += dt * v.x;
-        p.y += dt * v.y;
-        p.z += dt * v.z;
+        p.x = fma(dt, v.x, p.x);
+        p.y = fma(dt, v.y, p.y);
+        p.z = fma(dt, v.z, p.z);
     }
+}
+
+// Half kick v += (dt / 2) (kappa / m) F, one rounding per component.  Every
+// kernel that kicks uses this form, so a block that ends after a step and a
+// block that starts with a kick give the same velocities as one block that
+// runs through (a product used twice would otherwise be rounded on its own
+// in one kernel and fused into the addition in another).
+__device__ __forceinline__ void half_kick(double hk, double fx, double fy, double fz, double4& v)
+{
+    v.x = fma(hk, fx, v.x);
+    v.y = fma(hk, fy, v.y);
+    v.z = fma(hk, fz, v.z);
 }
 
 __device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, int mode, int forces, int nstep,
@@ -451,16 +464,11 @@ __device__ __forceinline__ void integrate_atom(const Sys& S, int a, double dt, i
     const double fy = (double)(long long)qy * (1.0 / kFixScale);
     const double fz = (double)(long long)qz * (1.0 / kFixScale);
     if (forces) S.frc[a] = make_double4(fx, fy, fz, 0.0);
-    if (mode >= 1) {
-        v.x += 0.5 * dt * ki * fx;
-        v.y += 0.5 * dt * ki * fy;
-        v.z += 0.5 * dt * ki * fz;
-    }
+    const double hk = 0.5 * dt * ki;
+    if (mode >= 1) half_kick(hk, fx, fy, fz, v);
     k = 0.5 * S.mass[a] * (v.x * v.x + v.y * v.y + v.z * v.z) / kKappa;
     if (mode == 2) {
-        v.x += 0.5 * dt * ki * fx;
-        v.y += 0.5 * dt * ki * fy;
-        v.z += 0.5 * dt * ki * fz;
+        half_kick(hk, fx, fy, fz, v);
         drift_atom(S, dt, ki, z, p, v);
         S.pos[a] = p;
         const float dx = (float)p.x - r0.x, dy = (float)p.y - r0.y, dz = (float)p.z - r0.z;
@@ -595,9 +603,7 @@ __global__ __launch_bounds__(256) void k_kickdrift(Sys S, double dt)
     double4 p = S.pos[a];
     const double ki = S.kinv[a];
     const double3 z = S.gamma > 0.0 ? langevin_noise(S.seed, S.perm[a], nstep) : make_double3(0.0, 0.0, 0.0);
-    v.x += 0.5 * dt * ki * f.x;
-    v.y += 0.5 * dt * ki * f.y;
-    v.z += 0.5 * dt * ki * f.z;
+    half_kick(0.5 * dt * ki, f.x, f.y, f.z, v);
     drift_atom(S, dt, ki, z, p, v);
     S.vel[a] = v;
     S.pos[a] = p;
