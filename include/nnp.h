@@ -181,6 +181,23 @@ nnp_status nnp_compute_device(nnp_context* ctx, const void* d_pos, int d_pos_is_
 nnp_status nnp_energy_device(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy, int keep);
 nnp_status nnp_forces_device(nnp_context* ctx, double* d_forces);
 
+/* Allocation-free stored mode, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): nnp_energy_device(ctx, d_pos, d_pos_is_f64, d_energy, 1) with
+ * G and dE/dG kept in a static device array of the library instead of
+ * context buffers allocated on first use.  The array holds at most 8,192
+ * atoms ([2][8192][384] float, 24 MiB per GPU, held until the process ends);
+ * a larger context gets NNP_ERR_ARG before any device work.  The call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * its first call on a device looks up the array's address there.
+ * nnp_forces_device then runs the adjoint from the array.  Every call on one
+ * GPU, from any context, shares that GPU's array: a later call replaces the
+ * kept G and dE/dG, after which nnp_forces_device of the earlier context
+ * returns NNP_ERR_STATE; calls of different host threads or streams that
+ * overlap on one GPU race.  Arguments, results and stream as for
+ * nnp_energy_device. */
+nnp_status nnp_energy_device_static(nnp_context* ctx, const void* d_pos, int d_pos_is_f64, double* d_energy);
+
 /* Periodic boundary conditions (the force provider's compute(positions, box)
  * contract, Methods): box = host [3] double, the edges (A) of an orthorhombic
  * box with one corner at the origin, or NULL for the gas phase (the default).

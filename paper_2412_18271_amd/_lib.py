@@ -21,7 +21,7 @@ RETURN_MODES = {"energy_forces": 3, "energy": 1}
 
 #: Every function the header declares.
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nnp_energy_device",
-           "nnp_forces_device", "nnp_set_state",
+           "nnp_forces_device", "nnp_energy_device_static", "nnp_set_state",
            "nnp_get_state", "nnp_step", "nnp_capture", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
            "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels", "nnp_time_steps",
            "nnp_set_thermostat", "nnp_set_box", "nnp_add_force", "nnp_clear_forces",
@@ -99,6 +99,7 @@ def load():
         "nnp_compute_device": (st, [vp, vp, ctypes.c_int, vp, vp]),
         "nnp_energy_device": (st, [vp, vp, ctypes.c_int, vp, ctypes.c_int]),
         "nnp_forces_device": (st, [vp, vp]),
+        "nnp_energy_device_static": (st, [vp, vp, ctypes.c_int, vp]),
         "nnp_set_state": (st, [vp, P(d), P(d)]),
         "nnp_get_state": (st, [vp, P(d), P(d), P(d), P(d), P(d)]),
         "nnp_step": (st, [vp, d, i32, i32]),

@@ -130,6 +130,13 @@ class Context:
         self._check(self._lib.nnp_energy_device(self._h, ctypes.c_void_p(d_pos), int(pos_is_f64),
                                                 ctypes.c_void_p(d_energy), 1 if keep else 0))
 
+    def energy_device_static(self, d_pos: int, pos_is_f64: bool, d_energy: int):
+        """Stored-mode energy (like energy_device(keep=True)) with G and
+        dE/dG in the library's static device array: allocates nothing; at
+        most 8,192 atoms; a later call on the same GPU replaces the kept data."""
+        self._check(self._lib.nnp_energy_device_static(self._h, ctypes.c_void_p(d_pos), int(pos_is_f64),
+                                                       ctypes.c_void_p(d_energy)))
+
     def forces_device(self, d_forces: int):
         self._check(self._lib.nnp_forces_device(self._h, ctypes.c_void_p(d_forces)))
 

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <sstream>
@@ -39,6 +40,27 @@ struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
 };
+
+// Scratch of the allocation-free stored-mode evaluation
+// (nnp_energy_device_static): the descriptors G and dE/dG of at most
+// kStaticAtoms atoms, [2][n][384] float, 24 MiB.  Each GPU the library runs
+// on holds its own copy until the process ends.  Host code never uses the
+// array's name as an address: the per-device address comes from
+// hipGetSymbolAddress on the first call on that device (StaticScratch).
+constexpr int kStaticAtoms = 8192;
+constexpr int kStaticDevices = 64;
+static __device__ __align__(256) float scratch[2 * (size_t)kStaticAtoms * kNumFeat];
+
+// Per device: the address of `scratch` on that GPU, and which context's
+// G / dE/dG it holds (the last call's; a later call from any context on the
+// same GPU replaces them).
+struct StaticScratch {
+    float* ptr = nullptr;
+    const nnp_context* owner = nullptr;
+    unsigned long long gen = 0;
+};
+StaticScratch g_static[kStaticDevices];
+std::mutex g_static_mu;
 
 }  // namespace
 
@@ -73,7 +95,10 @@ struct nnp_context {
     Sys S{};
     bool forces_current = false;
     bool kick_pending = false;  // previous block ended after a completed step (mode 1)
-    int diff_state = 0;         // 0: none, 1: energy evaluated (recompute), 2: energy + kept G, dE/dG
+    int diff_state = 0;         // 0: none, 1: energy evaluated (recompute), 2: energy + kept G, dE/dG,
+                                // 3: as 2 with G, dE/dG in the static scratch (nnp_energy_device_static)
+    int static_dev = -1;        // GPU whose static scratch holds this context's G, dE/dG (state 3)
+    unsigned long long static_gen = 0;  // that scratch's use count when this context filled it
     // captured MD blocks by (steps, dt, path, dtype, tile, friction, kT, seed)
     std::map<std::tuple<int, double, int, int, int, double, double, unsigned long long>, hipGraphExec_t> graphs;
     // extra force providers (caller callbacks and their device buffers)
@@ -974,6 +999,10 @@ oom:
 void nnp_destroy(nnp_context* c)
 {
     if (!c) return;
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static[c->static_dev].owner == c) g_static[c->static_dev].owner = nullptr;
+    }
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& b : c->bufs) (void)hipFree(b.p);
@@ -1010,12 +1039,70 @@ nnp_status nnp_energy_device(nnp_context* c, const void* d_pos, int is_f64, doub
     return NNP_OK;
 }
 
+nnp_status nnp_energy_device_static(nnp_context* c, const void* d_pos, int is_f64, double* d_energy)
+{
+    if (!c) return NNP_ERR_ARG;
+    if (!d_pos || !d_energy) return fail(c, NNP_ERR_ARG, "d_pos and d_energy are required");
+    if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions once with nnp_set_state or nnp_compute first");
+    if (c->n > kStaticAtoms)
+        return fail(c, NNP_ERR_ARG, "nnp_energy_device_static holds at most " + std::to_string(kStaticAtoms) +
+                                        " atoms (context has " + std::to_string(c->n) + ")");
+    int dev = 0;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticDevices) return fail(c, NNP_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+    float* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        StaticScratch& x = g_static[dev];
+        if (!x.ptr) {
+            // once per device, with that device current: the array's address
+            // on this GPU
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) return hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            x.ptr = static_cast<float*>(p);
+        }
+        x.owner = c;
+        x.gen += 1;
+        c->static_dev = dev;
+        c->static_gen = x.gen;
+        base = x.ptr;
+    }
+    // the kernels write every element of G and dE/dG they later read:
+    // nothing in the scratch has to start at zero
+    Sys S = c->S;
+    S.G = base;
+    S.dG = base + (size_t)c->n * kNumFeat;
+    HIP_TRY(c, launch_positions_in(S, d_pos, is_f64 ? 1 : 0, c->stream));
+    HIP_TRY(c, launch_invalidate_lists(S, c->stream));
+    HIP_TRY(c, launch_store_forward(S, mode_of(c), c->T, c->stream));
+    HIP_TRY(c, launch_gather_integrate(S, 0.0, 0, c->stream, false));
+    HIP_TRY(c, launch_energy_out(S, d_energy, c->stream));
+    c->diff_state = 3;
+    c->forces_current = false;
+    c->kick_pending = false;
+    return NNP_OK;
+}
+
 nnp_status nnp_forces_device(nnp_context* c, double* d_forces)
 {
     if (!c) return NNP_ERR_ARG;
     if (!d_forces) return fail(c, NNP_ERR_ARG, "d_forces is required");
     if (c->diff_state == 0) return fail(c, NNP_ERR_STATE, "call nnp_energy_device first");
-    if (c->diff_state == 2) {
+    if (c->diff_state == 3) {
+        // allocation-free stored mode: dE/dG sits in the device's static
+        // scratch, unless a later call has reused it
+        Sys S = c->S;
+        {
+            std::lock_guard<std::mutex> lk(g_static_mu);
+            const StaticScratch& x = g_static[c->static_dev];
+            if (x.owner != c || x.gen != c->static_gen)
+                return fail(c, NNP_ERR_STATE, "the static scratch was reused by a later nnp_energy_device_static call");
+            S.G = x.ptr;
+            S.dG = x.ptr + (size_t)c->n * kNumFeat;
+        }
+        HIP_TRY(c, launch_adjoint(S, c->stream));
+    } else if (c->diff_state == 2) {
         // stored mode: the pair list and reverse slots of the forward are
         // current; the adjoint reads the kept dE/dG
         HIP_TRY(c, launch_adjoint(c->S, c->stream));
