@@ -93,8 +93,16 @@ typedef enum { NNP_MLP_FP32 = 0, NNP_MLP_BF16 = 1, NNP_MLP_FP8 = 2, NNP_MLP_BF16
  *                   adjoint), descriptors and dE/dG round-trip through HBM;
  *   NNP_PATH_FUSED: one kernel per evaluation; a workgroup takes a tile of
  *                   atoms of one element through descriptors, network and
- *                   adjoint with every intermediate held in LDS. */
-typedef enum { NNP_PATH_PLAIN = 0, NNP_PATH_FUSED = 1 } nnp_path;
+ *                   adjoint with every intermediate held in LDS;
+ *   NNP_PATH_SPLIT: three kernels: descriptors of small tiles (pooled angular
+ *                   work) -> G in HBM; the network over wide tiles of up to
+ *                   network_tile atoms of one element, each weight fragment
+ *                   serving all of them -> dE/dG in HBM; the adjoint of the
+ *                   small tiles.  BF16 and split-BF16 networks only (else
+ *                   NNP_ERR_UNSUPPORTED at creation).  Built for large
+ *                   systems, where the fused kernel's per-tile weight reads
+ *                   and its one workgroup per compute unit bound throughput. */
+typedef enum { NNP_PATH_PLAIN = 0, NNP_PATH_FUSED = 1, NNP_PATH_SPLIT = 2 } nnp_path;
 
 typedef struct {
     int32_t n_atoms;             /* total atoms over all molecules, > 0 */
@@ -116,15 +124,19 @@ typedef struct {
                                     <= 256; 0 selects 192 */
     int32_t atoms_per_tile;      /* atoms per workgroup: 4, 8, 10 or, with the BF16 and
                                     split-BF16 networks, 16 (fused path); 8 or 16 (plain
-                                    path); 0 selects 16 (plain) or, for the fused path, 10
-                                    when that gives at most one workgroup per compute unit
-                                    and 8 would not, else 8 */
+                                    path); 4, 5, 7 or 10 (descriptor and adjoint kernels of
+                                    the split path); 0 selects 16 (plain), 5 (split) or, for
+                                    the fused path, 10 when that gives at most one workgroup
+                                    per compute unit and 8 would not, else 8 */
     void* stream;                /* hipStream_t to run on (see use_stream) */
     int32_t use_stream;          /* nonzero: run on `stream` even when it is NULL (the null
                                     stream, e.g. PyTorch's default stream); zero: a NULL
                                     stream means a stream created and owned by the context.
                                     Multi-step graphs cannot be captured on the null stream:
                                     nnp_step then launches its kernels directly. */
+    int32_t network_tile;        /* split path: atoms per workgroup of the network kernel,
+                                    16, 32, 48 or 64; 0 selects 64.  Ignored by the other
+                                    paths. */
 } nnp_params;
 
 /* Creates a context: validates params, sorts atoms into the internal order,
@@ -311,11 +323,21 @@ nnp_status nnp_debug_atom_energies(nnp_context* ctx, double* Ei);
 /* Bytes of device memory the context holds (buffers, weights, graphs' inputs). */
 nnp_status nnp_device_bytes(nnp_context* ctx, int64_t* bytes);
 
-/* Times the candidate launch configurations (atoms per workgroup) on the
- * current positions and keeps the fastest; if cache_path is not NULL the
- * choice is read from / appended to that JSON-lines file, keyed by atom
- * count bucket, molecule count, path and dtype.  Synchronises. */
-nnp_status nnp_autotune(nnp_context* ctx, const char* cache_path);
+/* Times the candidate kernel configurations on the current positions and
+ * keeps the fastest:
+ *   plain path: atoms per network tile 8 or 16;
+ *   fused path, FP32 / FP8 networks: atoms per workgroup 4, 8, 10;
+ *   fused or split path, BF16 / split-BF16 networks: the fused kernel with
+ *     4, 8, 10 or 16 atoms per workgroup, and the split path with 4, 5, 7 or
+ *     10 atoms per descriptor / adjoint workgroup times 32 or 64 atoms per
+ *     network workgroup (the path may change between fused and split: same
+ *     arithmetic, results equal to rounding).
+ * If cache_path is not NULL the choice is read from / appended to that
+ * JSON-lines file, keyed by the power-of-two buckets of the atom and molecule
+ * counts, the path family, the network dtype and periodicity; a cached
+ * choice is applied without timing.  choice (may be NULL) receives
+ * {path, atoms_per_tile, network_tile, from_cache}.  Synchronises. */
+nnp_status nnp_autotune(nnp_context* ctx, const char* cache_path, int32_t* choice);
 
 /* Kernel timing on the context stream with HIP events, at the current
  * positions: runs one evaluation to make the pair list current, then times

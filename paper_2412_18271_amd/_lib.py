@@ -16,7 +16,7 @@ NNP_OK = 0
 STATUS_NAMES = {0: "NNP_OK", 1: "NNP_ERR_ARG", 2: "NNP_ERR_NONFINITE", 3: "NNP_ERR_UNSUPPORTED",
                 4: "NNP_ERR_OOM", 5: "NNP_ERR_HIP", 6: "NNP_ERR_STATE"}
 DTYPES = {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
-PATHS = {"plain": 0, "fused": 1}
+PATHS = {"plain": 0, "fused": 1, "split": 2}
 RETURN_MODES = {"energy_forces": 3, "energy": 1}
 
 #: Every function the header declares.
@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("atoms_per_tile", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("use_stream", ctypes.c_int32),
+        ("network_tile", ctypes.c_int32),
     ]
 
 
@@ -109,7 +110,7 @@ def load():
         "nnp_debug_descriptors": (st, [vp, P(d), P(ctypes.c_float)]),
         "nnp_debug_atom_energies": (st, [vp, P(d)]),
         "nnp_device_bytes": (st, [vp, P(i64)]),
-        "nnp_autotune": (st, [vp, ctypes.c_char_p]),
+        "nnp_autotune": (st, [vp, ctypes.c_char_p, P(i32)]),
         "nnp_time_kernels": (st, [vp, i32, P(d)]),
         "nnp_time_steps": (st, [vp, d, i32, P(d)]),
         "nnp_set_thermostat": (st, [vp, d, d, ctypes.c_uint64]),

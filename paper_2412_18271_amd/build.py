@@ -17,7 +17,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["nnp_kernels.hip", "nnp_api.hip"]
+SOURCES = ["nnp_kernels.hip", "nnp_network.hip", "nnp_api.hip"]
 LIB = os.path.join(HERE, "libnnp_hip.so")
 ARCH = os.environ.get("NNP_OFFLOAD_ARCH", "gfx950")
 

@@ -27,7 +27,7 @@ class Context:
     def __init__(self, species, masses, weights, mol_offsets=None, dtype: str = "fp32",
                  path: str = "fused", rebuild_every: int = 20, skin: float = 1.0,
                  max_neighbors: int = 0, atoms_per_tile: int = 0, stream: Optional[int] = None,
-                 return_mode: str = "energy_forces"):
+                 return_mode: str = "energy_forces", network_tile: int = 0):
         self._lib = _lib.load()
         self._sp = np.ascontiguousarray(species, dtype=np.int32)
         self._m = np.ascontiguousarray(masses, dtype=np.float64)
@@ -59,6 +59,7 @@ class Context:
         p.atoms_per_tile = int(atoms_per_tile)
         p.stream = stream if stream else None
         p.use_stream = 0 if stream is None else 1
+        p.network_tile = int(network_tile)
         h = ctypes.c_void_p()
         s = self._lib.nnp_create(ctypes.byref(p), ctypes.byref(h))
         if s != _lib.NNP_OK:
@@ -259,7 +260,14 @@ class Context:
         return int(b.value)
 
     def autotune(self, cache_path: Optional[str] = None):
-        self._check(self._lib.nnp_autotune(self._h, cache_path.encode() if cache_path else None))
+        """Times the candidate kernel configurations and keeps the fastest
+        (or applies the cached choice); returns it as a dict."""
+        ch = (ctypes.c_int32 * 4)()
+        self._check(self._lib.nnp_autotune(self._h, cache_path.encode() if cache_path else None, ch))
+        names = {v: k for k, v in _lib.PATHS.items()}
+        self.path = names[ch[0]]
+        return {"path": self.path, "atoms_per_tile": int(ch[1]), "network_tile": int(ch[2]),
+                "from_cache": bool(ch[3])}
 
     def time_steps(self, dt: float, n: int):
         """n event-timed MD steps without a graph: average ms per step of

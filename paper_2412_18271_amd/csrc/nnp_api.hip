@@ -68,6 +68,7 @@ struct nnp_context {
     std::string err;
     // configuration
     int n = 0, nmol = 0, cap = 160, T = 16;
+    int nblk = 4;         // split path: 16-atom column blocks per network workgroup
     bool T_auto = false;  // atoms per tile chosen at layout
     // tiles on the host: table and the atom of every column (kTileCap per tile)
     std::vector<int4> tiles;
@@ -100,7 +101,7 @@ struct nnp_context {
     int static_dev = -1;        // GPU whose static scratch holds this context's G, dE/dG (state 3)
     unsigned long long static_gen = 0;  // that scratch's use count when this context filled it
     // captured MD blocks by (steps, dt, path, dtype, tile, friction, kT, seed)
-    std::map<std::tuple<int, double, int, int, int, double, double, unsigned long long>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, double, int, int, int, int, double, double, unsigned long long>, hipGraphExec_t> graphs;
     // extra force providers (caller callbacks and their device buffers)
     struct Extra {
         nnp_force_fn fn;
@@ -228,6 +229,11 @@ bool fused_tile_ok(int T, nnp_dtype d)
     return T == 4 || T == 8 || T == 10 || (T == 16 && (d == NNP_MLP_BF16 || d == NNP_MLP_BF16_SPLIT));
 }
 
+// Atoms per descriptor / adjoint workgroup of the split path (8 waves up to
+// 7 atoms, 16 waves for 10) and its network's column blocks.
+bool split_tile_ok(int T) { return T == 4 || T == 5 || T == 7 || T == 10; }
+bool split_dtype_ok(int d) { return d == NNP_MLP_BF16 || d == NNP_MLP_BF16_SPLIT; }
+
 std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
 {
     std::vector<int4> seq;
@@ -292,7 +298,10 @@ nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
 // lightest atom of the lightest tile, while that lowers the heavier of the
 // two; the work per atom comes from the last evaluation.  Deterministic (a
 // function of the recorded work).  Synchronises the context stream.
-bool balanced_tiles(const nnp_context* c) { return c->path == NNP_PATH_FUSED && c->T == 10; }
+bool balanced_tiles(const nnp_context* c)
+{
+    return (c->path == NNP_PATH_FUSED && c->T == 10) || c->path == NNP_PATH_SPLIT;
+}
 
 nnp_status rebalance_tiles(nnp_context* c)
 {
@@ -435,6 +444,18 @@ nnp_status setup_grids(nnp_context* c, const double* pos)
     return upload_tile_mol(c);
 }
 
+// Network tiles of the split path: up to 16 nblk consecutive atoms of one
+// element, in the same die-contiguous order as the tiles.  Synchronous.
+nnp_status upload_wide_tiles(nnp_context* c, const std::vector<int>& elem)
+{
+    if (c->path != NNP_PATH_SPLIT || !c->S.wtiles) return NNP_OK;
+    const std::vector<int4> wt = make_tiles(elem, 16 * c->nblk);
+    c->S.nwtiles = (int)wt.size();
+    c->S.wide_blk = c->nblk;
+    HIP_TRY(c, hipMemcpy((void*)c->S.wtiles, wt.data(), sizeof(int4) * wt.size(), hipMemcpyHostToDevice));
+    return NNP_OK;
+}
+
 // Builds the internal order from the first positions and uploads every
 // per-atom constant.
 nnp_status lay_out(nnp_context* c, const double* pos)
@@ -514,6 +535,8 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     {
         const nnp_status ts = upload_tiles(c, tiles);
         if (ts != NNP_OK) return ts;
+        const nnp_status ws = upload_wide_tiles(c, elem);
+        if (ws != NNP_OK) return ws;
     }
     HIP_TRY(c, hipMemcpy((void*)S.perm, perm_dev.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     // the context stream does not synchronise with the null stream
@@ -522,16 +545,35 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     return NNP_OK;
 }
 
-// Rebuilds the tile table for a new atoms-per-tile value.
-nnp_status retile(nnp_context* c, int T)
+// Buffers of the split path (G, dE/dG, network tiles), allocated on first use.
+nnp_status split_buffers(nnp_context* c)
 {
+    hipError_t e = hipSuccess;
+    Sys& S = c->S;
+    if (!S.G) S.G = (float*)dev_alloc(c, sizeof(float) * (size_t)c->n * kNumFeat, &e);
+    if (e == hipSuccess && !S.dG) S.dG = (float*)dev_alloc(c, sizeof(float) * (size_t)c->n * kNumFeat, &e);
+    if (e == hipSuccess && !S.wtiles) S.wtiles = (const int4*)dev_alloc(c, sizeof(int4) * ((size_t)c->n / 16 + 8), &e);
+    if (e != hipSuccess) return hip_fail(c, e, "split-path buffers");
+    return NNP_OK;
+}
+
+// Rebuilds the tile tables for a new path / atoms-per-tile / network tile.
+nnp_status retile(nnp_context* c, int T, nnp_path path, int nblk)
+{
+    if (path == NNP_PATH_SPLIT) {
+        const nnp_status bs = split_buffers(c);
+        if (bs != NNP_OK) return bs;
+    }
     c->T = T;
+    c->path = path;
+    c->nblk = nblk;
     if (!c->laid_out) return NNP_OK;
     std::vector<int> elem(c->n);
     for (int k = 0; k < c->n; ++k) elem[k] = c->species[c->perm[k]];
     const std::vector<int4> tiles = make_tiles(elem, T);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    const nnp_status ts = upload_tiles(c, tiles);
+    nnp_status ts = upload_tiles(c, tiles);
+    if (ts == NNP_OK) ts = upload_wide_tiles(c, elem);
     if (ts != NNP_OK) return ts;
     HIP_TRY(c, hipDeviceSynchronize());
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
@@ -674,7 +716,7 @@ int mode_of(const nnp_context* c)
 
 hipError_t enqueue_eval(nnp_context* c, bool grad)
 {
-    return launch_eval(c->S, c->path == NNP_PATH_FUSED ? 1 : 0, mode_of(c), c->T, grad, c->stream);
+    return launch_eval(c->S, (int)c->path, mode_of(c), c->T, grad, c->stream);
 }
 
 // Evaluation at the current positions without integration (forces, energies).
@@ -760,7 +802,8 @@ constexpr int kGraphBlock = 100;
 // on first use, then cached by everything its kernel arguments depend on).
 nnp_status block_graph(nnp_context* c, double dt, int len, hipGraphExec_t* out)
 {
-    const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T, c->S.gamma, c->S.kT, c->S.seed);
+    const auto key = std::make_tuple(len, dt, (int)c->path, (int)c->dtype, c->T, c->nblk, c->S.gamma, c->S.kT,
+                                     c->S.seed);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         hipGraph_t g;
@@ -863,7 +906,9 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
     const int dt = enum_raw(&p->mlp_dtype), pa = enum_raw(&p->path), rm = enum_raw(&p->return_mode);
     if (dt != NNP_MLP_FP32 && dt != NNP_MLP_BF16 && dt != NNP_MLP_BF16_SPLIT && dt != NNP_MLP_FP8)
         return msg = "unknown mlp_dtype", NNP_ERR_ARG;
-    if (pa != NNP_PATH_PLAIN && pa != NNP_PATH_FUSED) return msg = "unknown path", NNP_ERR_ARG;
+    if (pa != NNP_PATH_PLAIN && pa != NNP_PATH_FUSED && pa != NNP_PATH_SPLIT) return msg = "unknown path", NNP_ERR_ARG;
+    if (pa == NNP_PATH_SPLIT && !split_dtype_ok(dt))
+        return msg = "the split path runs the BF16 and split-BF16 networks only", NNP_ERR_UNSUPPORTED;
     if (rm != 0 && rm != NNP_RETURN_ENERGY && rm != NNP_RETURN_ENERGY_FORCES)
         return msg = "unknown return_mode", NNP_ERR_ARG;
     if (p->rebuild_every < 1) return msg = "rebuild_every must be >= 1", NNP_ERR_ARG;
@@ -873,6 +918,11 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
         return msg = "atoms_per_tile of the fused path must be 0, 4, 8, 10 or (BF16 networks) 16", NNP_ERR_ARG;
     if (p->path == NNP_PATH_PLAIN && p->atoms_per_tile != 0 && p->atoms_per_tile != 8 && p->atoms_per_tile != 16)
         return msg = "atoms_per_tile of the plain path must be 0, 8 or 16", NNP_ERR_ARG;
+    if (p->path == NNP_PATH_SPLIT && p->atoms_per_tile != 0 && !split_tile_ok(p->atoms_per_tile))
+        return msg = "atoms_per_tile of the split path must be 0, 4, 5, 7 or 10", NNP_ERR_ARG;
+    if (p->network_tile != 0 && p->network_tile != 16 && p->network_tile != 32 && p->network_tile != 48 &&
+        p->network_tile != 64)
+        return msg = "network_tile must be 0, 16, 32, 48 or 64", NNP_ERR_ARG;
     return NNP_OK;
 }
 
@@ -891,7 +941,9 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     c->n = p->n_atoms;
     c->nmol = p->n_molecules;
     c->cap = p->max_neighbors ? p->max_neighbors : 192;
-    c->T = p->atoms_per_tile ? p->atoms_per_tile : (p->path == NNP_PATH_FUSED ? 8 : 16);
+    c->T = p->atoms_per_tile ? p->atoms_per_tile
+                             : (p->path == NNP_PATH_FUSED ? 8 : p->path == NNP_PATH_SPLIT ? 5 : 16);
+    c->nblk = p->network_tile ? p->network_tile / 16 : 4;
     c->T_auto = p->atoms_per_tile == 0 && p->path == NNP_PATH_FUSED;
     c->dtype = p->mlp_dtype;
     c->path = p->path;
@@ -968,6 +1020,10 @@ nnp_status nnp_create(const nnp_params* p, nnp_context** out)
     if (c->path == NNP_PATH_PLAIN) {
         ALLOC(G, float*, n * kNumFeat)
         ALLOC(dG, float*, n * kNumFeat)
+    }
+    if (c->path == NNP_PATH_SPLIT && split_buffers(c) != NNP_OK) {
+        e = hipErrorOutOfMemory;
+        goto oom;
     }
 #undef ALLOC
     {
@@ -1569,7 +1625,7 @@ nnp_status nnp_time_steps(nnp_context* c, double dt, int32_t nsteps, double* ms)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) e = launch_kickdrift(c->S, dt, c->stream);
     for (int i = 0; i < nsteps && e == hipSuccess; ++i) {
-        e = launch_eval(c->S, c->path == NNP_PATH_FUSED ? 1 : 0, mode_of(c), c->T, true, c->stream, ev[4 * i],
+        e = launch_eval(c->S, (int)c->path, mode_of(c), c->T, true, c->stream, ev[4 * i],
                         ev[4 * i + 1]);
         if (e == hipSuccess)
             e = launch_gather_integrate(c->S, dt, i == nsteps - 1 ? 1 : 2, c->stream, true, ev[4 * i + 2],
@@ -1596,39 +1652,79 @@ nnp_status nnp_time_steps(nnp_context* c, double dt, int32_t nsteps, double* ms)
     return check_device_flags(c);
 }
 
-nnp_status nnp_autotune(nnp_context* c, const char* cache_path)
+nnp_status nnp_autotune(nnp_context* c, const char* cache_path, int32_t* choice)
 {
     if (!c) return NNP_ERR_ARG;
     if (!c->laid_out) return fail(c, NNP_ERR_STATE, "set positions before autotuning");
-    const std::string key = "n" + std::to_string(c->n) + "_m" + std::to_string(c->nmol) + "_p" +
-                            std::to_string((int)c->path) + "_d" + std::to_string((int)c->dtype);
+    // systems whose atom and molecule counts fall in the same power-of-two
+    // buckets share a tuned configuration; fused and split tune together
+    auto bucket = [](int v) {
+        int b = 0;
+        while ((2 << b) <= v) ++b;
+        return b;
+    };
+    const bool bf = split_dtype_ok(c->dtype);
+    const int family = c->path == NNP_PATH_PLAIN ? 0 : 1;
+    const std::string key = "nb" + std::to_string(bucket(c->n)) + "_mb" + std::to_string(bucket(c->nmol)) + "_f" +
+                            std::to_string(family) + "_d" + std::to_string((int)c->dtype) + "_pbc" +
+                            std::to_string(c->S.periodic ? 1 : 0);
+    struct Cand {
+        nnp_path path;
+        int T, nblk;
+    };
+    auto valid = [&](const Cand& k) {
+        if (family == 0) return k.path == NNP_PATH_PLAIN && (k.T == 8 || k.T == 16);
+        if (k.path == NNP_PATH_FUSED) return fused_tile_ok(k.T, c->dtype);
+        return k.path == NNP_PATH_SPLIT && bf && split_tile_ok(k.T) && k.nblk >= 1 && k.nblk <= 4;
+    };
+    auto apply = [&](const Cand& k, bool cached) {
+        nnp_status s = retile(c, k.T, k.path, k.nblk);
+        if (s != NNP_OK) return s;
+        if (choice) {
+            choice[0] = (int32_t)k.path;
+            choice[1] = k.T;
+            choice[2] = 16 * k.nblk;
+            choice[3] = cached ? 1 : 0;
+        }
+        return NNP_OK;
+    };
+    auto field = [](const std::string& line, const char* name, int* out) {
+        const std::string pat = std::string("\"") + name + "\": ";
+        const size_t p = line.find(pat);
+        if (p == std::string::npos) return false;
+        *out = std::atoi(line.c_str() + p + pat.size());
+        return true;
+    };
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
         while (std::getline(in, line)) {
-            const std::string pat = "\"key\": \"" + key + "\"";
-            if (line.find(pat) == std::string::npos) continue;
-            const size_t p = line.find("\"atoms_per_tile\": ");
-            if (p == std::string::npos) continue;
-            const int T = std::atoi(line.c_str() + p + 18);
-            if (c->path == NNP_PATH_FUSED ? fused_tile_ok(T, c->dtype) : (T == 8 || T == 16)) return retile(c, T);
+            if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+            int pa = 0, T = 0, nt = 0;
+            if (!field(line, "path", &pa) || !field(line, "atoms_per_tile", &T) || !field(line, "network_tile", &nt))
+                continue;
+            const Cand k{(nnp_path)pa, T, nt / 16};
+            if (valid(k)) return apply(k, true);
         }
     }
-    std::vector<int> cand;
-    if (c->path == NNP_PATH_FUSED) {
-        for (int T : {4, 8, 10, 16})
-            if (fused_tile_ok(T, c->dtype)) cand.push_back(T);
+    std::vector<Cand> cand;
+    if (family == 0) {
+        cand = {{NNP_PATH_PLAIN, 8, c->nblk}, {NNP_PATH_PLAIN, 16, c->nblk}};
     } else {
-        cand = {8, 16};
+        for (int T : {4, 8, 10, 16})
+            if (fused_tile_ok(T, c->dtype)) cand.push_back({NNP_PATH_FUSED, T, c->nblk});
+        if (bf)
+            for (int T : {4, 5, 7, 10})
+                for (int nb : {2, 4}) cand.push_back({NNP_PATH_SPLIT, T, nb});
     }
     double best = 1e300;
-    int bestT = c->T;
+    Cand bestk = {c->path, c->T, c->nblk};
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     std::ostringstream times;
-    for (int T : cand) {
-        nnp_status s = retile(c, T);
+    for (const Cand& k : cand) {
+        nnp_status s = retile(c, k.T, k.path, k.nblk);
         if (s != NNP_OK) return s;
         HIP_TRY(c, enqueue_eval(c, true));  // warm-up (also builds the lists)
         HIP_TRY(c, launch_gather_integrate(c->S, 0.0, 0, c->stream));
@@ -1642,23 +1738,26 @@ nnp_status nnp_autotune(nnp_context* c, const char* cache_path)
         HIP_TRY(c, hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-        times << (times.tellp() > 0 ? ", " : "") << "\"" << T << "\": " << ms / reps;
+        times << (times.tellp() > 0 ? ", " : "") << "\""
+              << (k.path == NNP_PATH_SPLIT ? "split" : k.path == NNP_PATH_FUSED ? "fused" : "plain") << "/" << k.T;
+        if (k.path == NNP_PATH_SPLIT) times << "x" << 16 * k.nblk;
+        times << "\": " << ms / reps;
         if (ms < best) {
             best = ms;
-            bestT = T;
+            bestk = k;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    nnp_status s = retile(c, bestT);
+    nnp_status s = apply(bestk, false);
     if (s != NNP_OK) return s;
     if (!c->extra.empty()) c->forces_current = false;  // the timed evaluations had no extra forces
     nnp_status f = check_device_flags(c);
     if (f != NNP_OK) return f;
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
-        o << "{\"key\": \"" << key << "\", \"atoms_per_tile\": " << bestT << ", \"ms_per_eval\": {" << times.str()
-          << "}}\n";
+        o << "{\"key\": \"" << key << "\", \"path\": " << (int)bestk.path << ", \"atoms_per_tile\": " << bestk.T
+          << ", \"network_tile\": " << 16 * bestk.nblk << ", \"ms_per_eval\": {" << times.str() << "}}\n";
     }
     return NNP_OK;
 }

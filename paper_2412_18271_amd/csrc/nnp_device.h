@@ -185,15 +185,21 @@ __device__ __forceinline__ void build_list(const Sys& S, int a)
 // least one of them with a mask of those it passes for; each atom's wave
 // then writes its list from the kept atoms that carry its bit: the same
 // candidates, tested by the same function in the same order, as build_list.
-constexpr int kScanRoundsMax = 4;  // kSharedScanCap / 1024 threads
+constexpr int kScanRoundsMax = 4;  // candidates per thread: CAP / NT (4096 / 1024 or 2048 / 512)
 
-struct SharedScan {
-    int idx[kSharedScanCap];       // kept atoms, ascending
-    unsigned mask[kSharedScanCap]; // bit i: within the list radius of tile atom i
+template <int CAP>
+struct SharedScanT {
+    int idx[CAP];        // kept atoms, ascending
+    unsigned mask[CAP];  // bit i: within the list radius of tile atom i
     double tx[kTileCap], ty[kTileCap], tz[kTileCap];
     int ta[kTileCap], tm[kTileCap];  // tile atoms and their molecules
     int wcnt[kScanRoundsMax][16];    // kept atoms per (round, wave)
 };
+using SharedScan = SharedScanT<kSharedScanCap>;
+
+// Candidate capacity of the shared scan of an NT-thread workgroup.
+template <int NT>
+constexpr int kScanCap = NT >= 1024 ? kSharedScanCap : kSharedScanCap / 2;
 
 // Number of kept atoms, or -1 (nothing kept, workgroup-uniform) when the
 // tile has no shared-scan molecule m (S.tile_mol) or its atoms turn out not
@@ -201,10 +207,12 @@ struct SharedScan {
 // comes from the host's table, so the molecule's ranges and the candidates'
 // positions are requested without waiting for the tile atoms' molecules,
 // which are only checked; three barriers in all.
-template <int NT>
-__device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms, int cnt, SharedScan& sc, int tid)
+template <int NT, int CAP = kScanCap<NT>>
+__device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms, int cnt, SharedScanT<CAP>& sc,
+                                           int tid)
 {
-    static_assert(NT == 1024 && kScanRoundsMax * NT >= kSharedScanCap, "one candidate per thread and round");
+    constexpr int kRounds = CAP / NT;
+    static_assert(kRounds * NT == CAP && kRounds <= kScanRoundsMax && NT / 64 <= 16, "candidates per thread");
     if (m < 0) return -1;
     int2 rg[kNumSpecies];
     int cum[kNumSpecies + 1];
@@ -214,13 +222,15 @@ __device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms
         rg[e] = S.mrange[m * kNumSpecies + e];
         cum[e + 1] = cum[e] + (rg[e].y - rg[e].x);
     }
-    const bool nogrid = S.molgrid[m] < 0;
-    const int total = min(cum[kNumSpecies], kSharedScanCap);
+    // a molecule with a cell grid or more candidates than CAP is scanned by
+    // each atom: decided (workgroup-uniformly) before anything is written
+    if (S.molgrid[m] >= 0 || cum[kNumSpecies] > CAP) return -1;
+    const int total = cum[kNumSpecies];
     // every position this thread tests is requested before any is tested
-    double4 pc[kScanRoundsMax];
-    int cc[kScanRoundsMax];
+    double4 pc[kRounds];
+    int cc[kRounds];
 #pragma unroll
-    for (int r = 0; r < kScanRoundsMax; ++r) {
+    for (int r = 0; r < kRounds; ++r) {
         const int q = r * NT + tid;
         cc[r] = -1;
         pc[r] = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -243,14 +253,17 @@ __device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms
         sc.tm[tid] = S.mol[a];
     }
     __syncthreads();
-    bool ok = nogrid && cum[kNumSpecies] <= kSharedScanCap;
+    bool ok = true;
     for (int i = 0; i < cnt; ++i) ok = ok && sc.tm[i] == m;
-    if (!ok) return -1;  // workgroup-uniform
+    if (!ok) {  // workgroup-uniform; the barrier lets every thread finish reading tm
+        __syncthreads();
+        return -1;
+    }
     const int wave = tid >> 6;
-    unsigned mk[kScanRoundsMax];
-    unsigned long long bal[kScanRoundsMax];
+    unsigned mk[kRounds];
+    unsigned long long bal[kRounds];
 #pragma unroll
-    for (int r = 0; r < kScanRoundsMax; ++r) {
+    for (int r = 0; r < kRounds; ++r) {
         mk[r] = 0;
         if (cc[r] >= 0)
             for (int i = 0; i < cnt; ++i)
@@ -263,7 +276,7 @@ __device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms
     __syncthreads();
     int nl = 0;
 #pragma unroll
-    for (int r = 0; r < kScanRoundsMax; ++r) {
+    for (int r = 0; r < kRounds; ++r) {
         int off = nl, tot = 0;
         for (int w = 0; w < NT / 64; ++w) {
             if (w < wave) off += sc.wcnt[r][w];
@@ -282,7 +295,8 @@ __device__ __forceinline__ int shared_scan(const Sys& S, int m, const int* atoms
 
 // Pair list of atom a, column `bit` of its tile, from the atoms kept by
 // shared_scan.
-__device__ __forceinline__ void build_list_shared(const Sys& S, int a, int bit, const SharedScan& sc, int nl)
+template <int CAP>
+__device__ __forceinline__ void build_list_shared(const Sys& S, int a, int bit, const SharedScanT<CAP>& sc, int nl)
 {
     const int lane = lane_id();
     int count = 0;

@@ -135,6 +135,10 @@ struct Sys {
     const int* tile_atoms;  // [ntiles][kTileCap] atom in each column of a tile
     const int* tile_mol;    // [ntiles] the molecule of all of a tile's atoms when it is scanned without a
                             // cell grid and has at most kSharedScanCap atoms, else -1
+    // split evaluation: network tiles of up to 16 wide_blk consecutive atoms of
+    // one element {first atom, count, element, 0}
+    const int4* wtiles;
+    int nwtiles, wide_blk;
     int* work;              // [n] angular pairs + radial entries / 2 at the last evaluation
     int* nbr;
     int* ncnt;
@@ -153,9 +157,9 @@ struct Sys {
     const void* wfrag;  // 4 * 2 * FragLayout::Count BF16 fragments of 1 KiB (hi, lo)
     const void* wfrag8; // 4 * FragLayout::Count E4M3 fragments of 512 B
     const float* wscale8;  // [4][6] inverse E4M3 weight scales (layers F1 F2 F3 B3 B2 B1)
-    // plain-path intermediates
-    float* G;   // [n][384]
-    float* dG;  // [n][384]
+    // plain- and split-path intermediates (internal atom order)
+    float* G;   // [n][384] descriptors
+    float* dG;  // [n][384] dE/dG
     // cell lists of large molecules
     const int* molgrid;      // [nmol] grid of the molecule, -1: brute-force candidate scan
     const CellGrid* grids;

@@ -273,6 +273,135 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
     }
 }
 
+// ---------------------------------------------------------------- split ---
+//
+// Split evaluation: the descriptor half and the adjoint half of the pooled
+// kernel as two kernels with the network between them over wide tiles
+// (k_mlp_wide): G and dE/dG go through HBM (L2 / MALL at these sizes), and
+// without the network's buffers a workgroup needs a third to a half of the
+// LDS, so several tiles share a CU and overlap their dependent chains of
+// memory, LDS and ALU work.  Tiles of T <= 7 atoms run 8 waves (512 threads),
+// tiles of 10 atoms 16 waves; the last wave plans the pooled angular runs.
+
+template <int T>
+constexpr int kSplitThreads = T <= 7 ? 512 : 1024;
+// force-merge table beyond the dE/dG rows (floats)
+template <int T>
+constexpr int kSplitTableExtra = T <= 7 ? 3072 : kPoolTableExtra;
+
+template <int T>
+struct DescSmem {
+    static constexpr int NT = kSplitThreads<T>;
+    union __attribute__((aligned(16))) {
+        struct {
+            float G[T * kLdG];
+            unsigned long long accI[T * 320];
+        } d;
+        SharedScanT<kScanCap<NT>> scan;  // candidates of a shared rebuild, before the descriptors
+    } u;
+    Env env[T];
+    PoolPlan<T> plan;
+};
+
+// First kernel: pair list (when due), environments, radial and pooled
+// angular features of a tile -> S.G rows (internal order), work per atom.
+template <int T>
+__global__ __launch_bounds__(kSplitThreads<T>) void k_desc_pooled(Sys S)
+{
+    constexpr int NT = kSplitThreads<T>;
+    static_assert(NT > 64 * T, "a wave per atom and a planning wave");
+    __shared__ __attribute__((aligned(16))) DescSmem<T> sm;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int4 tile = S.tiles[blockIdx.x];
+    const int* col = S.tile_atoms + blockIdx.x * kTileCap;
+    const bool act = wave < tile.y;
+    const int w = wave < T ? wave : 0;
+    const int a = act ? col[wave] : 0;
+    const bool rb = rebuild_due(S.st, S.rebuild_every);
+    Env& E = sm.env[w];
+    const int nl = rb ? shared_scan<NT>(S, S.tile_mol[blockIdx.x], col, tile.y, sm.u.scan, tid) : -1;
+    if (act) {
+        if (rb && S.molgrid[S.mol[a]] < 0) {
+            if (nl >= 0) {
+                build_list_shared(S, a, wave, sm.u.scan, nl);
+                __threadfence_block();
+                load_env(S, a, E);
+            } else {
+                build_list_env(S, a, E);
+            }
+        } else {
+            load_env(S, a, E);
+        }
+        if (lane == 0) S.work[a] = E.nA * (E.nA - 1) / 2 + E.nR / 2;
+    }
+    if (nl >= 0) __syncthreads();
+    for (int i = tid; i < T * kLdG; i += NT) sm.u.d.G[i] = 0.f;
+    for (int i = tid; i < T * 320; i += NT) sm.u.d.accI[i] = 0ull;
+    __syncthreads();
+    if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
+    if (act) radial_features(E, sm.u.d.G + w * kLdG);
+    __syncthreads();
+    angular_features_pooled<T>(sm.env, sm.plan, sm.u.d.accI, tid);
+    __syncthreads();
+    angular_store_pooled<T>(sm.u.d.accI, sm.u.d.G, tid, NT);
+    __syncthreads();
+    for (int i = tid; i < T * (kNumFeat / 4); i += NT) {
+        const int t = i / (kNumFeat / 4), f = (i - t * (kNumFeat / 4)) * 4;
+        if (t < tile.y)
+            *reinterpret_cast<float4*>(S.G + (size_t)col[t] * kNumFeat + f) =
+                *reinterpret_cast<const float4*>(sm.u.d.G + t * kLdG + f);
+    }
+}
+
+template <int T>
+struct AdjSmem {
+    float G[T * kLdG];               // dE/dG rows, then (with Gx) the force-merge table
+    float Gx[kSplitTableExtra<T>];
+    float facc[T * 3 * kRadMax];                 // radial part of the forces
+    unsigned long long faccA[T * kAngMax * 3];   // angular part (fixed point)
+    Env env[T];
+    PoolPlan<T> plan;
+};
+
+// Third kernel: environments from the lists the first kernel left, dE/dG
+// rows from S.dG, radial and pooled angular adjoint, force merge, HBM
+// fixed-point sums.
+template <int T>
+__global__ __launch_bounds__(kSplitThreads<T>) void k_adj_pooled(Sys S)
+{
+    constexpr int NT = kSplitThreads<T>;
+    use_die_copy(S);
+    __shared__ __attribute__((aligned(16))) AdjSmem<T> sm;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int4 tile = S.tiles[blockIdx.x];
+    const int* col = S.tile_atoms + blockIdx.x * kTileCap;
+    const bool act = wave < tile.y;
+    const int w = wave < T ? wave : 0;
+    const int a = act ? col[wave] : 0;
+    Env& E = sm.env[w];
+    if (act) load_env(S, a, E);
+    for (int i = tid; i < T * (kNumFeat / 4); i += NT) {
+        const int t = i / (kNumFeat / 4), f = (i - t * (kNumFeat / 4)) * 4;
+        if (t < tile.y)
+            *reinterpret_cast<float4*>(sm.G + t * kLdG + f) =
+                *reinterpret_cast<const float4*>(S.dG + (size_t)col[t] * kNumFeat + f);
+    }
+    for (int i = tid; i < T * kAngMax * 3; i += NT) sm.faccA[i] = 0ull;
+    __syncthreads();
+    if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
+    float* fa = sm.facc + w * 3 * kRadMax;
+    if (act) adjoint_radial(E, sm.G + w * kLdG, fa);
+    __syncthreads();
+    adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.faccA, tid);
+    __syncthreads();
+    const ForceTable ft = force_table(sm.G, sizeof(sm.G) + sizeof(sm.Gx));
+    table_clear(ft, tid, NT);
+    __syncthreads();
+    if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.faccA + (size_t)wave * kAngMax * 3);
+    __syncthreads();
+    table_flush(S, ft, tid, NT);
+}
+
 // Network of one tile of atoms: G from HBM, dE/dG (when GRAD) and E_i to HBM.
 template <int T, int MODE, bool GRAD>
 __global__ __launch_bounds__(64 * T) void k_mlp(Sys S)
@@ -965,6 +1094,27 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(8, 3)
         NNP_FUSED(10, 3)
 #undef NNP_FUSED
+        return hipErrorInvalidValue;
+    }
+    if (path == 2) {
+        // descriptors -> S.G, wide-tile network -> S.Ei, S.dG, adjoint
+        if (mode != 1 && mode != 2) return hipErrorInvalidValue;
+#define NNP_SPLIT(TT)                                                                                         \
+    if (T == TT) {                                                                                            \
+        hipExtLaunchKernelGGL(k_desc_pooled<TT>, dim3(S.ntiles), dim3(kSplitThreads<TT>), 0, s, ev0, nullptr, \
+                              0, S);                                                                          \
+        hipError_t ew = launch_mlp_wide(S, mode, S.wide_blk, grad, s, nullptr, grad ? nullptr : ev1);         \
+        if (ew != hipSuccess) return ew;                                                                      \
+        if (grad)                                                                                             \
+            hipExtLaunchKernelGGL(k_adj_pooled<TT>, dim3(S.ntiles), dim3(kSplitThreads<TT>), 0, s, nullptr,   \
+                                  ev1, 0, S);                                                                 \
+        return hipGetLastError();                                                                             \
+    }
+        NNP_SPLIT(4)
+        NNP_SPLIT(5)
+        NNP_SPLIT(7)
+        NNP_SPLIT(10)
+#undef NNP_SPLIT
         return hipErrorInvalidValue;
     }
     const int nb4 = (S.n + 3) / 4;

@@ -6,7 +6,8 @@
 namespace nnp {
 
 // One energy (and, if grad, force) evaluation at the current positions.
-// path 0 = plain (one kernel per stage), 1 = fused; mode 0 = FP32 VALU,
+// path 0 = plain (one kernel per stage), 1 = fused, 2 = split (descriptors,
+// wide-tile network, adjoint: three kernels); mode 0 = FP32 VALU,
 // 1 = BF16 MFMA, 2 = split BF16 MFMA (hi/lo operands, three products),
 // 3 = E4M3 MFMA with per-layer scales.
 // ev0 / ev1 (optional): events stamped by the first and the last kernel
@@ -35,5 +36,9 @@ hipError_t launch_extra_add(const Sys& S, const double* frc, const double* en, h
 // E4M3 encoding of n floats by the device conversion instruction (format check).
 hipError_t launch_fp8_encode(const float* x, int n, unsigned char* out, hipStream_t s);
 hipError_t launch_descriptors_only(const Sys& S, hipStream_t s);
+// Network of the split evaluation over S.wtiles (S.G -> S.Ei and, if grad,
+// S.dG); mode 1 = BF16, 2 = split BF16; nblk = S.wide_blk.
+hipError_t launch_mlp_wide(const Sys& S, int mode, int nblk, bool grad, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
 
 }  // namespace nnp

@@ -58,6 +58,7 @@ int main(void)
     BAD(weights_count, 10)
     BAD(mlp_dtype, (nnp_dtype)9)
     BAD(path, (nnp_path)4)
+    BAD(network_tile, 24)
     BAD(return_mode, (nnp_return)2)
     BAD(rebuild_every, 0)
     BAD(skin, -0.5)
@@ -86,7 +87,7 @@ int main(void)
     expect(nnp_capture(NULL, 0.5, 1) == NNP_ERR_ARG, "capture null");
     expect(nnp_set_state(NULL, pos, NULL) == NNP_ERR_ARG, "set_state null");
     expect(nnp_get_state(NULL, pos, NULL, NULL, NULL, NULL) == NNP_ERR_ARG, "get_state null");
-    expect(nnp_autotune(NULL, NULL) == NNP_ERR_ARG, "autotune null");
+    expect(nnp_autotune(NULL, NULL, NULL) == NNP_ERR_ARG, "autotune null");
     expect(strcmp(nnp_last_error(NULL), "null context") == 0, "last_error null");
     for (int s = 0; s <= 7; ++s) expect(nnp_status_string((nnp_status)s) != NULL, "status string");
     nnp_destroy(NULL);

@@ -76,12 +76,27 @@ def _params(P, s, **kw):
     ("max_neighbors", 300, 1),
     ("atoms_per_tile", 12, 1),
     ("atoms_per_tile", 6, 1),
+    ("network_tile", 20, 1),
+    ("network_tile", 128, 1),
 ])
 def test_create_rejects_invalid_params(field, value, status):
     import paper_2412_18271_amd as P
     lib = P.load()
     s = synth.make_config("mol22")
     p, keep = _params(P, s, **{field: value})
+    h = ctypes.c_void_p()
+    assert lib.nnp_create(ctypes.byref(p), ctypes.byref(h)) == status
+    assert not h.value
+
+
+@pytest.mark.parametrize("dtype,tile,status", [(0, 0, 3), (2, 0, 3), (3, 8, 1), (1, 16, 1)])
+def test_split_path_validation(dtype, tile, status):
+    """The split path runs the BF16 networks only (FP32 / FP8: unsupported)
+    with 4, 5, 7 or 10 atoms per descriptor / adjoint workgroup."""
+    import paper_2412_18271_amd as P
+    lib = P.load()
+    s = synth.make_config("mol22")
+    p, keep = _params(P, s, path=2, mlp_dtype=dtype, atoms_per_tile=tile)
     h = ctypes.c_void_p()
     assert lib.nnp_create(ctypes.byref(p), ctypes.byref(h)) == status
     assert not h.value

@@ -16,6 +16,8 @@ import subprocess
 
 import pytest
 
+from paper_2412_18271_amd import build
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANG = "/opt/rocm/llvm/bin/clang"
@@ -49,8 +51,8 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
         san += ["-Xarch_host", f]
     _run([HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + san +
-         ["-I", os.path.join(ROOT, "include"), "-shared", os.path.join(csrc, "nnp_api.hip"),
-          os.path.join(csrc, "nnp_kernels.hip"), "-o", lib], timeout=900)
+         ["-I", os.path.join(ROOT, "include"), "-shared"] + [os.path.join(csrc, f) for f in build.SOURCES] +
+         ["-o", lib], timeout=900)
     exe = str(tmp_path / "abi_check")
     _run([CLANG, "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "abi_sanitize_check.c"),
