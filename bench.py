@@ -72,7 +72,7 @@ MI355X_FP8_MFMA_TFLOPS = 5000.0
 MI355X_HBM_GBS = 8000.0
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_pooled_bf16x3_cluster2500_traffic.md")
-KERNEL_SOURCES = ("nnp_kernels.hip", "nnp_device.h", "nnp_internal.h")
+KERNEL_SOURCES = ("nnp_kernels.hip", "nnp_network.hip", "nnp_device.h", "nnp_internal.h")
 
 
 def log(*a):
@@ -167,17 +167,22 @@ def rate_summary(seconds, steps, units=1):
             "repeats": rates, "spread": (max(rates) - min(rates)) / med}
 
 
-def run_variant(P, s, dtype, path, steps, warmup, refs, tune=None):
+def run_variant(P, s, dtype, path, steps, warmup, refs, tune=True):
+    """One network dtype / path: the autotuner picks the kernel configuration
+    (path within the fused / split family, atoms per workgroup, network
+    tile) on the initial positions, then the force errors on the reference
+    configurations, the timed MD steps and the event-timed kernels."""
     ctx = P.Context.from_system(s, dtype=dtype, path=path)
     try:
+        tuned = None
+        if tune:
+            ctx.set_state(s.pos, s.vel)
+            tuned = ctx.autotune(None)
+            log("   autotune:", tuned)
         errs = []
         for pos, F_ref in refs:
             _, F = ctx.compute(pos)
             errs.append(float(np.abs(F - F_ref).max()))
-        tuned = None
-        if tune is not None:
-            ctx.set_state(s.pos, s.vel)
-            tuned = ctx.autotune(tune)
         secs, st = timed_steps(ctx, s, steps, warmup)
         rs = rate_summary(secs, steps)
         U, K = ctx.energy_log(min(steps + 1, 4096))
@@ -185,7 +190,7 @@ def run_variant(P, s, dtype, path, steps, warmup, refs, tune=None):
         final_finite = bool(np.isfinite(ctx.get_state()["pos"]).all())
         kt = event_timed(ctx, s, warmup, steps)
         return {
-            "dtype": dtype, "path": path, "steps_per_s": rs["rate"],
+            "dtype": dtype, "path": ctx.path, "requested_path": path, "steps_per_s": rs["rate"],
             "ms_per_step": rs["ms_per_step"], "repeats_steps_per_s": rs["repeats"], "spread": rs["spread"],
             "autotune": tuned, "max_force_err": errs[0],
             "max_force_err_snapshots": max(errs[1:]) if len(errs) > 1 else None,
@@ -236,6 +241,34 @@ def periodic_leg(P, dtype, path, steps, warmup):
         ctx.close()
 
 
+def large_leg(P, steps, warmup):
+    """The 23,000-atom cluster (cell lists), split-BF16 network, kernel
+    configuration from the autotuner: MD steps/s, the evaluation kernels'
+    event-timed duration and their VALU / MFMA rates against the peaks."""
+    import synth
+    s = synth.make_config("cluster23k")
+    ctx = P.Context.from_system(s, dtype="bf16x3", path="fused")
+    try:
+        ctx.set_state(s.pos, s.vel)
+        tuned = ctx.autotune(None)
+        log("   autotune:", tuned)
+        secs, st = timed_steps(ctx, s, steps, warmup, repeats=3)
+        rs = rate_summary(secs, steps)
+        kt = event_timed(ctx, s, warmup, steps)
+    finally:
+        ctx.close()
+    t = kt["eval_ms"] * 1e-3
+    valu = kt["radial_pairs"] * FLOP_RADIAL_PAIR + kt["angular_triples"] * FLOP_ANGULAR_TRIPLE
+    mlp = s.n_atoms * FLOP_MLP_ATOM
+    sol = valu / (MI355X_FP32_VECTOR_TFLOPS * 1e12) + mlp / (MI355X_BF16_MFMA_TFLOPS * 1e12)
+    return {"workload": "cluster23k: 23,000-atom gas-phase cluster, NVE dt 0.5 fs, rebuild 20 / skin 1 A",
+            "dtype": "bf16x3", "autotune": tuned, "steps_per_s": rs["rate"], "ms_per_step": rs["ms_per_step"],
+            "spread": rs["spread"], "ns_per_day": rs["rate"] * DT_FS * 86400 / 1e6,
+            "kernel_ms_eval": kt["eval_ms"], "kernel_ms_gather_vv": kt["gather_ms"],
+            "valu_tflops": valu / t / 1e12, "mlp_tflops": mlp / t / 1e12, "combined_frac": sol / t,
+            "rebuilds": st["rebuilds"]}
+
+
 def batch_leg(P, steps, warmup):
     """256 molecules of 10-300 atoms: molecule-steps/s of one batched context
     (one evaluation launch per step for all molecules, graph-replayed) against
@@ -246,6 +279,9 @@ def batch_leg(P, steps, warmup):
     out = {"n_molecules": M, "n_atoms": int(s.n_atoms), "steps": steps, "dtype": "bf16x3"}
     ctx = P.Context.from_system(s, dtype="bf16x3", path="fused")
     try:
+        ctx.set_state(s.pos, s.vel)
+        out["autotune"] = ctx.autotune(None)
+        log("   autotune:", out["autotune"])
         secs, _ = timed_steps(ctx, s, steps, warmup)
         rs = rate_summary(secs, steps, M)
         out["batched_molecule_steps_per_s"] = rs["rate"]
@@ -538,7 +574,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--variants", default=",".join("%s:%s" % v for v in VARIANTS))
     ap.add_argument("--profile-only", default=None,
-                    help="dtype:path; run only that variant's timed steps (for rocprofv3)")
+                    help="dtype:path[:atoms_per_tile[:network_tile]]; run only that variant's timed steps "
+                         "(for rocprofv3)")
+    ap.add_argument("--workload", default="cluster2500", help="with --profile-only: the synthetic system")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="with --profile-only: also run an elementwise kernel over this many MiB")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None)
@@ -579,8 +618,12 @@ def main():
 
     s = synth.make_config("cluster2500")
     if args.profile_only:
-        dtype, path = args.profile_only.split(":")
-        ctx = P.Context.from_system(s, dtype=dtype, path=path)
+        parts = args.profile_only.split(":")
+        dtype, path = parts[0], parts[1]
+        T = int(parts[2]) if len(parts) > 2 else 0
+        nt = int(parts[3]) if len(parts) > 3 else 0
+        s = synth.make_config(args.workload)
+        ctx = P.Context.from_system(s, dtype=dtype, path=path, atoms_per_tile=T, network_tile=nt)
         ctx.set_state(s.pos, s.vel)
         ctx.step(DT_FS, args.warmup, graph=True)
         ctx.step(DT_FS, args.steps, graph=True)
@@ -653,6 +696,10 @@ def main():
     log("periodic")
     out["periodic_box2500"] = periodic_leg(P, best["dtype"], best["path"], args.steps, args.warmup)
     log("  ", json.dumps(out["periodic_box2500"]))
+    if not args.no_large:
+        log("cluster23k")
+        out["cluster23k"] = large_leg(P, 200, 20)
+        log("  ", json.dumps(out["cluster23k"]))
     if not args.no_batch:
         log("batch256")
         out["batch256"] = batch_leg(P, 100, 20)

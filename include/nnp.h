@@ -266,7 +266,7 @@ nnp_status nnp_capture(nnp_context* ctx, double dt_fs, int32_t n_steps);
  * the calling function returns NNP_ERR_STATE; the evaluation is discarded,
  * and inside nnp_step the interrupted step leaves positions and velocities
  * mid-step: set the state again before stepping on).  The library adds them to the
- * network's forces (64-bit fixed point, 2^-32 eV/A, |component| < 2^30) and
+ * network's forces (64-bit fixed point, 2^-32 eV/A, |component| < 2^15) and
  * molecule energies (not to the per-atom energies).  The three buffers are
  * caller-owned device memory and, like `user`, must stay valid until
  * nnp_clear_forces or nnp_destroy (the paper's keep-alive rule for the

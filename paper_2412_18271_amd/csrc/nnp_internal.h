@@ -30,7 +30,13 @@ constexpr int kNumFeat = 384;   // 4 * 16 radial + 10 * 32 angular
 constexpr int kH1 = 160, kH2 = 128, kH3 = 96;
 
 constexpr double kFixScale = 4294967296.0;  // fixed-point force units per eV/A (2^32)
-constexpr float kFixMax = 1073741824.0f;    // largest accepted |force component| (2^30 eV/A)
+// Largest accepted |force component| of one fixed-point term (2^15 eV/A).
+// An atom's sum collects at most ~3.1e4 terms: up to 160 neighbours' energies
+// with a radial term and an angular term of at most 95 adds each, its own
+// energy's negated sum of the same, and up to 8 provider forces; 3.1e4 x 2^15
+// x 2^32 < 2^62, so no sum (nor the copies' total) can wrap int64.  A larger
+// term raises the non-finite flag instead of being added.
+constexpr float kFixMax = 32768.0f;
 constexpr float kCutRad = 5.2f;
 constexpr float kCutAng = 3.5f;
 constexpr float kEtaRad = 16.0f;
