@@ -330,10 +330,18 @@ def copy_calibration(mib):
     log("copy calibration: 3 x torch.neg over %d MiB (read %d MiB, write %d MiB)" % (mib, mib, mib))
 
 
-def pmc_summary(fetch_db, write_db, variant, mib, command):
+# Evaluation kernels per path (one launch each per evaluation; the split path's
+# traffic is the sum of its three kernels' per-dispatch means).
+EVAL_KERNELS = {"fused": [r"k_eval_(fused|pooled)<\d+, %d,"], "split": [r"k_desc_pooled<", r"k_mlp_wide<",
+                                                                       r"k_adj_pooled<"]}
+
+
+def pmc_summary(fetch_db, write_db, variant, mib, command, workload="cluster2500"):
     """Markdown summary of a FETCH_SIZE run and a WRITE_SIZE run: per-dispatch
-    KiB of the evaluation kernel, scaled by the calibration kernel's reading."""
-    dtype, path = variant.split(":")
+    KiB of the evaluation kernel(s), scaled by the calibration kernel's
+    reading."""
+    dtype, path = variant.split(":")[:2]
+    pats = [p % KERNEL_MODE[dtype] if "%d" in p else p for p in EVAL_KERNELS[path]]
 
     def per_kernel(db, counter):
         c = sqlite3.connect(db)
@@ -346,12 +354,12 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
         rows = per_kernel(db, counter)
         cal = [v for k, v in rows if "neg" in k and v > 0.25 * known_kib]
-        ker = [(k, v) for k, v in rows if "k_eval_" in k]
+        ker = [(k, v) for k, v in rows if any(re.search(p, k) for p in pats)]
         names = sorted({k for k, _ in ker})
-        mine = [v for k, v in ker if re.search(r"k_eval_(fused|pooled)<\d+, %d," % KERNEL_MODE[dtype], k)]
+        per = [[v for k, v in ker if re.search(p, k)] for p in pats]
         res[counter] = {"cal_kib": float(np.median(cal)) if cal else None,
-                        "kernel_kib": float(np.mean(mine)) if mine else None,
-                        "dispatches": len(mine), "names": names}
+                        "kernel_kib": float(sum(np.mean(x) for x in per)) if all(per) else None,
+                        "dispatches": min(len(x) for x in per), "names": names}
     fr = res["FETCH_SIZE"]
     wr = res["WRITE_SIZE"]
     f_factor = known_kib / fr["cal_kib"]
@@ -359,15 +367,15 @@ def pmc_summary(fetch_db, write_db, variant, mib, command):
     fetch_b = fr["kernel_kib"] * f_factor * 1024
     write_b = wr["kernel_kib"] * w_factor * 1024
     lines = [
-        "# Evaluation kernel HBM traffic, cluster2500 (2,500 atoms), %s network" % dtype,
+        "# Evaluation kernel HBM traffic, %s, %s network, %s path" % (workload, dtype, path),
         "",
         "Commands (run from the repository root, TMPDIR=/tmp):",
         "",
         "```",
         command.replace("COUNTER", "FETCH_SIZE"),
         command.replace("COUNTER", "WRITE_SIZE"),
-        "python3 bench.py --pmc-summary <fetch run db> <write run db> --variant %s --copy-calibration-mib %d"
-        % (variant, mib),
+        "python3 bench.py --pmc-summary <fetch run db> <write run db> --variant %s --workload %s "
+        "--copy-calibration-mib %d" % (variant, workload, mib),
         "```",
         "",
         "Calibration kernel: torch.neg over %d MiB of float32 (reads %d MiB, writes %d MiB)." % (mib, mib, mib),
@@ -398,7 +406,7 @@ def counter_summary(variant, stats_csv, dbs, mib, profile_args):
     WRITE_SIZE were taken next to the calibration kernel, the HBM rate
     against 8 TB/s."""
     import csv
-    dtype, path = variant.split(":")
+    dtype, path = variant.split(":")[:2]
     dur = {}
     with open(stats_csv) as fh:
         for row in csv.DictReader(fh):
@@ -601,7 +609,7 @@ def main():
 
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.variant,
-                    args.copy_calibration_mib or 256, args.pmc_command)
+                    args.copy_calibration_mib or 256, args.pmc_command, args.workload)
         return
 
     if args.counter_summary:

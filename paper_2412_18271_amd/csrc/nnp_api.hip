@@ -72,6 +72,7 @@ struct nnp_context {
     bool T_auto = false;  // atoms per tile chosen at layout
     // tiles on the host: table and the atom of every column (kTileCap per tile)
     std::vector<int4> tiles;
+    std::vector<int4> tiles_init;  // the table as made (rebalancing reorders tiles)
     std::vector<int> tile_atoms;
     std::vector<int> molgrid;  // grid of each molecule, -1: scanned without a cell grid
     nnp_dtype dtype = NNP_MLP_FP32;
@@ -282,6 +283,7 @@ nnp_status upload_tile_mol(nnp_context* c)
 nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
 {
     c->tiles = tiles;
+    c->tiles_init = tiles;
     c->tile_atoms.assign(tiles.size() * kTileCap, 0);
     for (size_t b = 0; b < tiles.size(); ++b)
         for (int i = 0; i < tiles[b].y; ++i) c->tile_atoms[b * kTileCap + i] = tiles[b].x + i;
@@ -340,9 +342,42 @@ nnp_status rebalance_tiles(nnp_context* c)
             changed = true;
         }
     }
-    if (changed)
+    // Schedule: workgroups start in index order and workgroup b runs on die
+    // b mod 8, so each die's entries (b = x, x + 8, ...) are reordered by
+    // their tiles' recorded work, heaviest first: long tiles start first and
+    // short ones fill the end of the launch (list scheduling by work).  A
+    // device-side queue (an atomic counter per die) gave the same order at
+    // the price of a contended atomic and a dependent load before every
+    // tile's first access; this order costs nothing on the device.
+    {
+        std::vector<long long> W(nt, 0);
+        for (int b = 0; b < nt; ++b)
+            for (int i = 0; i < c->tiles[b].y; ++i) W[b] += work[c->tile_atoms[(size_t)b * kTileCap + i]];
+        std::vector<int4> tiles2(c->tiles);
+        std::vector<int> atoms2(c->tile_atoms);
+        for (int x = 0; x < kXcds; ++x) {
+            std::vector<int> idx;
+            for (int b = x; b < nt; b += kXcds) idx.push_back(b);
+            std::vector<int> srt(idx);
+            std::stable_sort(srt.begin(), srt.end(), [&](int p, int q) { return W[p] > W[q]; });
+            for (size_t k = 0; k < idx.size(); ++k) {
+                if (srt[k] == idx[k]) continue;
+                tiles2[idx[k]] = c->tiles[srt[k]];
+                std::copy(c->tile_atoms.begin() + (size_t)srt[k] * kTileCap,
+                          c->tile_atoms.begin() + (size_t)(srt[k] + 1) * kTileCap,
+                          atoms2.begin() + (size_t)idx[k] * kTileCap);
+                changed = true;
+            }
+        }
+        c->tiles.swap(tiles2);
+        c->tile_atoms.swap(atoms2);
+    }
+    if (changed) {
+        HIP_TRY(c, hipMemcpyAsync((void*)c->S.tiles, c->tiles.data(), sizeof(int4) * c->tiles.size(),
+                                  hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync((void*)c->S.tile_atoms, c->tile_atoms.data(), sizeof(int) * c->tile_atoms.size(),
                                   hipMemcpyHostToDevice, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return changed ? upload_tile_mol(c) : NNP_OK;
 }
@@ -1189,7 +1224,7 @@ nnp_status nnp_set_state(nnp_context* c, const double* pos, const double* vel)
         // a new trajectory starts from the initial tiling with no recorded work
         if (balanced_tiles(c)) {
             HIP_TRY(c, hipStreamSynchronize(c->stream));
-            const nnp_status ts = upload_tiles(c, c->tiles);
+            const nnp_status ts = upload_tiles(c, std::vector<int4>(c->tiles_init));
             if (ts != NNP_OK) return ts;
             HIP_TRY(c, hipMemset(c->S.work, 0, sizeof(int) * c->n));
         }

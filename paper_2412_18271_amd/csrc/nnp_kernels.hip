@@ -15,6 +15,7 @@
 #include "nnp_device.h"
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cstddef>
 
 #include "nnp_launch.h"
@@ -200,17 +201,15 @@ template <int T>
 constexpr int kPoolThreads = 1024;
 
 template <int T, int MODE, bool GRAD>
-__global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
+__device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, MODE>& sm)
 {
     constexpr int NT = kPoolThreads<T>;
     static_assert(NT > 64 * T, "a wave per atom and a planning wave");
-    use_die_copy(S);
-    __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int4 tile = S.tiles[blockIdx.x];
+    const int4 tile = S.tiles[tb];
     const bool act = wave < tile.y;  // tile.y <= T
     const int w = wave < T ? wave : 0;
-    const int a = act ? S.tile_atoms[blockIdx.x * kTileCap + wave] : 0;
+    const int a = act ? S.tile_atoms[tb * kTileCap + wave] : 0;
     const bool rb = rebuild_due(S.st, S.rebuild_every);
     Env& E = sm.env[w];
     float* Grow = sm.G + w * kLdG;
@@ -222,9 +221,7 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
                   sizeof(SharedScan) <= sizeof(sm.G) + sizeof(sm.Gx) && offsetof(Smem, G) % 16 == 0,
                   "candidate list over G and Gx");
     SharedScan& scan = *reinterpret_cast<SharedScan*>(sm.G);
-    const int nl = rb ? shared_scan<NT>(S, S.tile_mol[blockIdx.x], S.tile_atoms + blockIdx.x * kTileCap, tile.y,
-                                        scan, tid)
-                      : -1;
+    const int nl = rb ? shared_scan<NT>(S, S.tile_mol[tb], S.tile_atoms + tb * kTileCap, tile.y, scan, tid) : -1;
     if (act) {
         if (rb && S.molgrid[S.mol[a]] < 0) {
             if (nl >= 0) {
@@ -273,6 +270,14 @@ __global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
     }
 }
 
+template <int T, int MODE, bool GRAD>
+__global__ __launch_bounds__(kPoolThreads<T>) void k_eval_pooled(Sys S)
+{
+    use_die_copy(S);
+    __shared__ __attribute__((aligned(16))) PooledSmem<T, MODE> sm;
+    pooled_tile<T, MODE, GRAD>(S, blockIdx.x, sm);
+}
+
 // ---------------------------------------------------------------- split ---
 //
 // Split evaluation: the descriptor half and the adjoint half of the pooled
@@ -306,20 +311,19 @@ struct DescSmem {
 // First kernel: pair list (when due), environments, radial and pooled
 // angular features of a tile -> S.G rows (internal order), work per atom.
 template <int T>
-__global__ __launch_bounds__(kSplitThreads<T>) void k_desc_pooled(Sys S)
+__device__ __forceinline__ void desc_tile(const Sys& S, int tb, DescSmem<T>& sm)
 {
     constexpr int NT = kSplitThreads<T>;
     static_assert(NT > 64 * T, "a wave per atom and a planning wave");
-    __shared__ __attribute__((aligned(16))) DescSmem<T> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int4 tile = S.tiles[blockIdx.x];
-    const int* col = S.tile_atoms + blockIdx.x * kTileCap;
+    const int4 tile = S.tiles[tb];
+    const int* col = S.tile_atoms + tb * kTileCap;
     const bool act = wave < tile.y;
     const int w = wave < T ? wave : 0;
     const int a = act ? col[wave] : 0;
     const bool rb = rebuild_due(S.st, S.rebuild_every);
     Env& E = sm.env[w];
-    const int nl = rb ? shared_scan<NT>(S, S.tile_mol[blockIdx.x], col, tile.y, sm.u.scan, tid) : -1;
+    const int nl = rb ? shared_scan<NT>(S, S.tile_mol[tb], col, tile.y, sm.u.scan, tid) : -1;
     if (act) {
         if (rb && S.molgrid[S.mol[a]] < 0) {
             if (nl >= 0) {
@@ -354,6 +358,13 @@ __global__ __launch_bounds__(kSplitThreads<T>) void k_desc_pooled(Sys S)
 }
 
 template <int T>
+__global__ __launch_bounds__(kSplitThreads<T>) void k_desc_pooled(Sys S)
+{
+    __shared__ __attribute__((aligned(16))) DescSmem<T> sm;
+    desc_tile<T>(S, blockIdx.x, sm);
+}
+
+template <int T>
 struct AdjSmem {
     float G[T * kLdG];               // dE/dG rows, then (with Gx) the force-merge table
     float Gx[kSplitTableExtra<T>];
@@ -367,14 +378,12 @@ struct AdjSmem {
 // rows from S.dG, radial and pooled angular adjoint, force merge, HBM
 // fixed-point sums.
 template <int T>
-__global__ __launch_bounds__(kSplitThreads<T>) void k_adj_pooled(Sys S)
+__device__ __forceinline__ void adj_tile(const Sys& S, int tb, AdjSmem<T>& sm)
 {
     constexpr int NT = kSplitThreads<T>;
-    use_die_copy(S);
-    __shared__ __attribute__((aligned(16))) AdjSmem<T> sm;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int4 tile = S.tiles[blockIdx.x];
-    const int* col = S.tile_atoms + blockIdx.x * kTileCap;
+    const int4 tile = S.tiles[tb];
+    const int* col = S.tile_atoms + tb * kTileCap;
     const bool act = wave < tile.y;
     const int w = wave < T ? wave : 0;
     const int a = act ? col[wave] : 0;
@@ -400,6 +409,14 @@ __global__ __launch_bounds__(kSplitThreads<T>) void k_adj_pooled(Sys S)
     if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.faccA + (size_t)wave * kAngMax * 3);
     __syncthreads();
     table_flush(S, ft, tid, NT);
+}
+
+template <int T>
+__global__ __launch_bounds__(kSplitThreads<T>) void k_adj_pooled(Sys S)
+{
+    use_die_copy(S);
+    __shared__ __attribute__((aligned(16))) AdjSmem<T> sm;
+    adj_tile<T>(S, blockIdx.x, sm);
 }
 
 // Network of one tile of atoms: G from HBM, dE/dG (when GRAD) and E_i to HBM.
@@ -1106,8 +1123,8 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         hipError_t ew = launch_mlp_wide(S, mode, S.wide_blk, grad, s, nullptr, grad ? nullptr : ev1);         \
         if (ew != hipSuccess) return ew;                                                                      \
         if (grad)                                                                                             \
-            hipExtLaunchKernelGGL(k_adj_pooled<TT>, dim3(S.ntiles), dim3(kSplitThreads<TT>), 0, s, nullptr,   \
-                                  ev1, 0, S);                                                                 \
+            hipExtLaunchKernelGGL(k_adj_pooled<TT>, dim3(S.ntiles), dim3(kSplitThreads<TT>), 0, s, nullptr, ev1, \
+                                  0, S);                                                                      \
         return hipGetLastError();                                                                             \
     }
         NNP_SPLIT(4)
