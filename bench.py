@@ -261,11 +261,14 @@ def large_leg(P, steps, warmup):
     valu = kt["radial_pairs"] * FLOP_RADIAL_PAIR + kt["angular_triples"] * FLOP_ANGULAR_TRIPLE
     mlp = s.n_atoms * FLOP_MLP_ATOM
     sol = valu / (MI355X_FP32_VECTOR_TFLOPS * 1e12) + mlp / (MI355X_BF16_MFMA_TFLOPS * 1e12)
+    var = "bf16x3:%s" % tuned["path"]
+    traffic = load_traffic(var, traffic_summary_path(var, "cluster23k"))
     return {"workload": "cluster23k: 23,000-atom gas-phase cluster, NVE dt 0.5 fs, rebuild 20 / skin 1 A",
             "dtype": "bf16x3", "autotune": tuned, "steps_per_s": rs["rate"], "ms_per_step": rs["ms_per_step"],
             "spread": rs["spread"], "ns_per_day": rs["rate"] * DT_FS * 86400 / 1e6,
             "kernel_ms_eval": kt["eval_ms"], "kernel_ms_gather_vv": kt["gather_ms"],
             "valu_tflops": valu / t / 1e12, "mlp_tflops": mlp / t / 1e12, "combined_frac": sol / t,
+            "traffic": traffic, "hbm_gbs_from_traffic": None if traffic is None else traffic / t / 1e9,
             "rebuilds": st["rebuilds"]}
 
 
@@ -467,11 +470,18 @@ def counter_summary(variant, stats_csv, dbs, mib, profile_args):
     print("\n".join(out))
 
 
-def load_traffic(variant):
+def traffic_summary_path(variant, workload):
+    """Committed HBM-traffic summary of a dtype:path on a workload."""
+    dtype, path = variant.split(":")[:2]
+    kern = "k_split" if path == "split" else "k_eval_pooled"
+    return os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.md" % (kern, dtype, workload))
+
+
+def load_traffic(variant, summary=None):
     """HBM bytes per launch from the committed counter summary, or None when
     it covers another variant or the kernel sources changed since."""
     try:
-        txt = open(TRAFFIC_SUMMARY).read()
+        txt = open(summary or TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     kv = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
