@@ -142,15 +142,22 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(NB
     const bf16x8* __restrict__ frl = fr + F::Count * 64;
     const int col = lane & 15, rq = (lane >> 4) * 4;
 
-    // G rows of the tile's atoms -> BF16 hi (and lo) rows; missing atoms zero
+    // G rows of the tile's atoms -> BF16 hi (and lo) rows; missing atoms
+    // zero.  Every load is issued before the first conversion.
     {
-        __bf16* ghi = sm.u.g;
-        __bf16* glo = sm.u.g + LO * NA * kLdG;
-        for (int i = tid; i < NA * (kNumFeat / 4); i += kWideThreads) {
-            const int c = i / (kNumFeat / 4), f = (i - c * (kNumFeat / 4)) * 4;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (c < cnt) v = *reinterpret_cast<const float4*>(S.G + (size_t)(first + c) * kNumFeat + f);
-            put_act4<SPLIT>(ghi, glo, c * kLdG + f, floatx4{v.x, v.y, v.z, v.w});
+        constexpr int PER = NA * (kNumFeat / 4) / kWideThreads;
+        static_assert(PER * kWideThreads == NA * (kNumFeat / 4), "whole float4 rows per thread");
+        float4 v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = tid + q * kWideThreads, c = i / (kNumFeat / 4), f = (i - c * (kNumFeat / 4)) * 4;
+            v[q] = c < cnt ? *reinterpret_cast<const float4*>(S.G + (size_t)(first + c) * kNumFeat + f)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = tid + q * kWideThreads, c = i / (kNumFeat / 4), f = (i - c * (kNumFeat / 4)) * 4;
+            put_act4<SPLIT>(sm.u.g, sm.u.g + LO * NA * kLdG, c * kLdG + f, floatx4{v[q].x, v[q].y, v[q].z, v[q].w});
         }
     }
     __syncthreads();
