@@ -921,16 +921,15 @@ struct PoolPlan {
 };
 
 // Group sizes, run length and lane ranges for the first nact atoms of the
-// tile, computed by one wave (lane: groups 2 lane and 2 lane + 1) while the
-// others do other work; the caller's next barrier publishes the plan.
-// C = ceil(W / (NT - 10 T)) for W pairs in all keeps the runs within the NT
-// lanes of the workgroup: sum_g ceil(cnt_g / C) < W / C + 10 T <= NT.
+// tile, computed by one wave (lane: groups GPL lane .. GPL lane + GPL - 1)
+// while the others do other work; the caller's next barrier publishes the
+// plan.  C = ceil(W / (NT - 10 T)) for W pairs in all keeps the runs within
+// the NT lanes of the workgroup: sum_g ceil(cnt_g / C) < W / C + 10 T <= NT.
 template <int T, int NT>
 __device__ __forceinline__ void pool_plan_wave(const Env* env, int nact, PoolPlan<T>& pl, int lane)
 {
-    constexpr int NG = T * 10, FREE = NT - NG;
+    constexpr int NG = T * 10, FREE = NT - NG, GPL = (NG + 63) / 64;
     static_assert(FREE > 0, "more lanes than groups");
-    static_assert(NG <= 128, "two groups per lane of the planning wave");
     auto group_size = [&](int g) {
         if (g >= NG || g / 10 >= nact) return 0;  // no atom in this column of the tile
         const Env& E = env[g / 10];
@@ -939,27 +938,36 @@ __device__ __forceinline__ void pool_plan_wave(const Env* env, int nact, PoolPla
         const int n1 = E.aseg[s1 + 1] - E.aseg[s1], n2 = E.aseg[s2 + 1] - E.aseg[s2];
         return s1 == s2 ? n1 * (n1 - 1) / 2 : n1 * n2;
     };
-    const int g0 = 2 * lane, g1 = 2 * lane + 1;
-    const int c0 = group_size(g0), c1 = group_size(g1);
-    int w = c0 + c1;
+    int c[GPL], w = 0;
+#pragma unroll
+    for (int i = 0; i < GPL; ++i) {
+        c[i] = group_size(GPL * lane + i);
+        w += c[i];
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
     const int C = w > FREE ? (w + FREE - 1) / FREE : 1;
-    const int r0 = (c0 + C - 1) / C, r1 = (c1 + C - 1) / C;
-    int incl = r0 + r1;
+    int r[GPL], mine = 0;
+#pragma unroll
+    for (int i = 0; i < GPL; ++i) {
+        r[i] = (c[i] + C - 1) / C;
+        mine += r[i];
+    }
+    int incl = mine;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const int v = __shfl_up(incl, off);
         if (lane >= off) incl += v;
     }
-    const int excl = incl - r0 - r1;
-    if (g0 < NG) {
-        pl.cnt[g0] = c0;
-        pl.first[g0] = excl;
-    }
-    if (g1 < NG) {
-        pl.cnt[g1] = c1;
-        pl.first[g1] = excl + r0;
+    int at = incl - mine;
+#pragma unroll
+    for (int i = 0; i < GPL; ++i) {
+        const int g = GPL * lane + i;
+        if (g < NG) {
+            pl.cnt[g] = c[i];
+            pl.first[g] = at;
+        }
+        at += r[i];
     }
     if (lane == 63) pl.first[NG] = incl;
     if (lane == 0) pl.C = C;

@@ -177,11 +177,24 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
 // hundred distinct receiving atoms, and a nearly full table probes long.
 constexpr int kPoolTableExtra = 10240;  // floats
 
+// Workgroup of the pooled kernel: 16 waves for a tile of 10 or 12 atoms; 8
+// waves for a tile of 5, whose LDS (70 KB) lets two tiles share a CU and
+// overlap their dependent chains of memory, LDS, MFMA and ALU work.  One wave
+// per atom loads the environments; the pooled angular work, the network's
+// output-row tiles and the force merge spread over all the waves.  12-atom
+// tiles fill 12 of the 16 MFMA columns (10 of 16 at 10 atoms) and so stream
+// the weight fragments for 20 % more atoms; their environments leave a
+// smaller force-merge table.
+template <int T>
+constexpr int kPoolThreads = T <= 7 ? 512 : 1024;
+template <int T>
+constexpr int kPoolTableFloats = T <= 7 ? 3072 : T <= 10 ? kPoolTableExtra : T == 12 ? 6016 : T == 13 ? 3200 : 256;
+
 template <int T, int MODE>
 struct PooledSmem {
     Env env[T];
     float G[T * kLdG];
-    float Gx[kPoolTableExtra];  // continues G for the force-merge table only
+    float Gx[kPoolTableFloats<T>];  // continues G for the force-merge table only
     PoolPlan<T> plan;
     union __attribute__((aligned(16))) {  // 16-byte LDS vector accesses
         typename MlpSmemOf<T, MODE>::type m;
@@ -193,12 +206,6 @@ struct PooledSmem {
     } u;
     float E[16];
 };
-
-// Workgroup of the pooled kernel: 16 waves for a tile of 10 atoms.  One wave
-// per atom loads the environments; the pooled angular work, the network's
-// output-row tiles and the force merge spread over all 16.
-template <int T>
-constexpr int kPoolThreads = 1024;
 
 template <int T, int MODE, bool GRAD>
 __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, MODE>& sm)
@@ -215,12 +222,16 @@ __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, 
     float* Grow = sm.G + w * kLdG;
 
     // a rebuild scans the molecule once for the whole tile when it can; the
-    // candidates overlay G and Gx until the barrier below
+    // candidates overlay G, Gx, the plan and the union (none of them is
+    // written before the barrier below, which ends the scan)
     using Smem = PooledSmem<T, MODE>;
-    static_assert(offsetof(Smem, Gx) == offsetof(Smem, G) + sizeof(sm.G) &&
-                  sizeof(SharedScan) <= sizeof(sm.G) + sizeof(sm.Gx) && offsetof(Smem, G) % 16 == 0,
-                  "candidate list over G and Gx");
-    SharedScan& scan = *reinterpret_cast<SharedScan*>(sm.G);
+    using Scan = SharedScanT<kScanCap<NT>>;
+    static_assert(offsetof(Smem, G) < offsetof(Smem, Gx) && offsetof(Smem, Gx) < offsetof(Smem, plan) &&
+                      offsetof(Smem, plan) < offsetof(Smem, u) &&
+                      sizeof(Scan) <= offsetof(Smem, u) + sizeof(sm.u) - offsetof(Smem, G) &&
+                      offsetof(Smem, G) % 16 == 0,
+                  "candidate list over G .. u");
+    Scan& scan = *reinterpret_cast<Scan*>(sm.G);
     const int nl = rb ? shared_scan<NT>(S, S.tile_mol[tb], S.tile_atoms + tb * kTileCap, tile.y, scan, tid) : -1;
     if (act) {
         if (rb && S.molgrid[S.mol[a]] < 0) {
@@ -1052,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
 // Tiles of 10 atoms (one workgroup per CU at 2,500 atoms) pool the angular
 // work; the other tile sizes keep one wave per atom throughout.
 template <int T>
-constexpr bool kPooledTile = T == 10;
+constexpr bool kPooledTile = T == 10 || T == 5 || T == 12 || T == 13 || T == 14;
 
 template <int T, int MODE, bool GRAD>
 static hipError_t launch_fused_t(const Sys& S, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
@@ -1097,19 +1108,35 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
     if (T == TT && mode == MM) return grad ? launch_fused_t<TT, MM, true>(S, s, ev0, ev1)    \
                                            : launch_fused_t<TT, MM, false>(S, s, ev0, ev1);
         NNP_FUSED(4, 0)
+        NNP_FUSED(5, 0)
         NNP_FUSED(8, 0)
         NNP_FUSED(10, 0)
+        NNP_FUSED(12, 0)
+        NNP_FUSED(13, 0)
+        NNP_FUSED(14, 0)
         NNP_FUSED(4, 1)
+        NNP_FUSED(5, 1)
         NNP_FUSED(8, 1)
         NNP_FUSED(10, 1)
+        NNP_FUSED(12, 1)
+        NNP_FUSED(13, 1)
+        NNP_FUSED(14, 1)
         NNP_FUSED(16, 1)
         NNP_FUSED(4, 2)
+        NNP_FUSED(5, 2)
         NNP_FUSED(8, 2)
         NNP_FUSED(10, 2)
+        NNP_FUSED(12, 2)
+        NNP_FUSED(13, 2)
+        NNP_FUSED(14, 2)
         NNP_FUSED(16, 2)
         NNP_FUSED(4, 3)
+        NNP_FUSED(5, 3)
         NNP_FUSED(8, 3)
         NNP_FUSED(10, 3)
+        NNP_FUSED(12, 3)
+        NNP_FUSED(13, 3)
+        NNP_FUSED(14, 3)
 #undef NNP_FUSED
         return hipErrorInvalidValue;
     }

@@ -64,7 +64,7 @@ int main(void)
     BAD(skin, -0.5)
     BAD(skin, NAN)
     BAD(max_neighbors, 257)
-    BAD(atoms_per_tile, 12)
+    BAD(atoms_per_tile, 11)
     BAD(species, NULL)
     BAD(masses, NULL)
     BAD(weights, NULL)

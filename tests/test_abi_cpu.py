@@ -74,7 +74,7 @@ def _params(P, s, **kw):
     ("rebuild_every", 0, 1),
     ("skin", -1.0, 1),
     ("max_neighbors", 300, 1),
-    ("atoms_per_tile", 12, 1),
+    ("atoms_per_tile", 11, 1),
     ("atoms_per_tile", 6, 1),
     ("network_tile", 20, 1),
     ("network_tile", 128, 1),

@@ -54,23 +54,33 @@ def test_autograd_forces_match_oracle(make_system, mode, dtype):
 
 def test_autograd_modes_agree_and_scale(make_system):
     """Recompute and stored modes give the same gradient; a weighted sum of
-    two molecules' energies scales each molecule's gradient."""
+    two molecules' energies scales each molecule's gradient.
+
+    With 8-atom tiles both modes sum each atom's descriptors in the same
+    order and agree to 1e-9.  The default tiles of a system this size (14
+    atoms, angular work pooled over the workgroup) sum the angular
+    descriptors in fixed point instead: rounding-level differences, bounded
+    by twice the split-BF16 force error against the oracle (3e-5 eV/A)."""
     import torch
     from paper_2412_18271_amd.autograd import NNPModel
     s = make_system("batch256")
     grads = {}
-    for mode in ("recompute", "store"):
-        m = NNPModel.from_system(s, dtype="bf16x3", mode=mode)
+    for mode, T in (("recompute", 8), ("store", 8), ("recompute", 0)):
+        m = NNPModel.from_system(s, dtype="bf16x3", mode=mode, atoms_per_tile=T)
         pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda", requires_grad=True)
         E = m(pos)
         w = torch.zeros_like(E)
         w[0], w[5] = 2.0, -0.5
         (E * w).sum().backward()
-        grads[mode] = pos.grad.cpu().numpy()
-    np.testing.assert_allclose(grads["recompute"], grads["store"], rtol=0, atol=1e-9)
+        grads[mode, T] = pos.grad.cpu().numpy()
+    np.testing.assert_allclose(grads["recompute", 8], grads["store", 8], rtol=0, atol=1e-9)
+    d = np.abs(grads["recompute", 0] - grads["store", 8]).max()
+    _say("default tiles against 8-atom tiles: max|d grad| %.2e" % d)
+    assert d <= 1e-4
     _, _, F0 = oracle.energy_forces(s.pos[s.molecule(0)], s.species[s.molecule(0)], s.weights)
-    np.testing.assert_allclose(grads["store"][s.molecule(0)], -2.0 * F0, atol=2e-3)
-    assert np.all(grads["store"][s.molecule(1)] == 0.0)
+    for key in grads:
+        np.testing.assert_allclose(grads[key][s.molecule(0)], -2.0 * F0, atol=2e-3)
+        assert np.all(grads[key][s.molecule(1)] == 0.0)
 
 
 def test_droplet100k_finite_differences_subcluster_and_memory(make_system):
@@ -126,4 +136,9 @@ def test_droplet100k_finite_differences_subcluster_and_memory(make_system):
     bytes_store = mstore.device_bytes()
     _say("device bytes: recompute %.1f MB, store %.1f MB" % (bytes_recompute / 1e6, bytes_store / 1e6))
     assert bytes_store - bytes_recompute >= 2 * 384 * 4 * s.n_atoms
-    np.testing.assert_allclose(g2, g, rtol=0, atol=1e-9)
+    # the recompute mode's default tiles pool the angular descriptor sums
+    # (fixed point) where the stored mode sums per atom: rounding-level
+    # differences (see test_autograd_modes_agree_and_scale)
+    d = np.abs(g2 - g).max()
+    _say("stored against recompute: max|d grad| %.2e" % d)
+    assert d <= 1e-4

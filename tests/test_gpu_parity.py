@@ -75,10 +75,13 @@ def test_descriptors_match_oracle(make_system):
 
 
 @pytest.mark.parametrize("path,dtype,T", [("plain", "fp32", 16), ("plain", "fp32", 8), ("fused", "fp32", 8),
-                                          ("fused", "fp32", 4), ("fused", "fp32", 10),
+                                          ("fused", "fp32", 4), ("fused", "fp32", 5), ("fused", "fp32", 10),
+                                          ("fused", "fp32", 12), ("fused", "fp32", 14),
                                           ("plain", "bf16", 16), ("fused", "bf16", 8), ("fused", "bf16", 4),
-                                          ("fused", "bf16", 10), ("plain", "bf16x3", 16), ("fused", "bf16x3", 8),
-                                          ("fused", "bf16x3", 4), ("fused", "bf16x3", 10), ("fused", "bf16x3", 16),
+                                          ("fused", "bf16", 5), ("fused", "bf16", 10), ("fused", "bf16", 12), ("plain", "bf16x3", 16),
+                                          ("fused", "bf16x3", 8), ("fused", "bf16x3", 4), ("fused", "bf16x3", 5),
+                                          ("fused", "bf16x3", 10), ("fused", "bf16x3", 12), ("fused", "bf16x3", 13),
+                                          ("fused", "bf16x3", 14), ("fused", "bf16x3", 16),
                                           ("fused", "bf16x3", 0)])
 @pytest.mark.parametrize("name", ["mol22", "cluster2500"])
 def test_energy_forces_match_oracle(oracle_cache, name, path, dtype, T):
@@ -196,16 +199,16 @@ def test_fp8_device_conversion_matches_host_encoder():
     assert same.all()
 
 
-@pytest.mark.parametrize("path", ["fused", "plain"])
-def test_fp8_network_error_reported(oracle_cache, path):
+@pytest.mark.parametrize("path,T", [("fused", 0), ("fused", 5), ("fused", 12), ("fused", 14), ("plain", 0)])
+def test_fp8_network_error_reported(oracle_cache, path, T):
     """FP8 (E4M3) network: errors against the oracle are reported; the
     path must stay finite and within an order of magnitude of BF16's."""
     s, Eo, Eio, Fo = oracle_cache("cluster2500")
-    ctx = _ctx(s, path=path, dtype="fp8")
+    ctx = _ctx(s, path=path, dtype="fp8", atoms_per_tile=T)
     E, F = ctx.compute(s.pos)
     dE = abs(E.sum() - Eo.sum()) / np.abs(Eio).sum()
     dF = np.abs(F - Fo).max()
-    _say("fp8 %s: |dE|/S %.3e  max|dF| %.3e  rms|dF| %.3e" % (path, dE, dF, np.sqrt(((F - Fo) ** 2).mean())))
+    _say("fp8 %s T=%d: |dE|/S %.3e  max|dF| %.3e  rms|dF| %.3e" % (path, T, dE, dF, np.sqrt(((F - Fo) ** 2).mean())))
     assert np.all(np.isfinite(F))
     assert dF <= 0.3
     ctx.close()
