@@ -262,7 +262,7 @@ def large_leg(P, steps, warmup):
     mlp = s.n_atoms * FLOP_MLP_ATOM
     sol = valu / (MI355X_FP32_VECTOR_TFLOPS * 1e12) + mlp / (MI355X_BF16_MFMA_TFLOPS * 1e12)
     var = "bf16x3:%s" % tuned["path"]
-    traffic = load_traffic(var, traffic_summary_path(var, "cluster23k"))
+    traffic = load_traffic(var, traffic_summary_path(var, "cluster23k"), tile_of_choice(tuned))
     return {"workload": "cluster23k: 23,000-atom gas-phase cluster, NVE dt 0.5 fs, rebuild 20 / skin 1 A",
             "dtype": "bf16x3", "autotune": tuned, "steps_per_s": rs["rate"], "ms_per_step": rs["ms_per_step"],
             "spread": rs["spread"], "ns_per_day": rs["rate"] * DT_FS * 86400 / 1e6,
@@ -339,6 +339,30 @@ EVAL_KERNELS = {"fused": [r"k_eval_(fused|pooled)<\d+, %d,"], "split": [r"k_desc
                                                                        r"k_adj_pooled<"]}
 
 
+def tile_of_kernels(names):
+    """Tile configuration named by the evaluation kernels seen: "10" (fused:
+    atoms per workgroup), "5x32" (split: descriptor / adjoint tile x network
+    tile), or None."""
+    fused = {int(m.group(1)) for n in names for m in [re.search(r"k_eval_(?:fused|pooled)<(\d+),", n)] if m}
+    desc = {int(m.group(1)) for n in names for m in [re.search(r"k_desc_pooled<(\d+)>", n)] if m}
+    wide = {int(m.group(1)) for n in names for m in [re.search(r"k_mlp_wide<(\d+),", n)] if m}
+    if len(fused) == 1 and not desc:
+        return "%d" % fused.pop()
+    if len(desc) == 1 and len(wide) == 1 and not fused:
+        return "%dx%d" % (desc.pop(), 16 * wide.pop())
+    return None
+
+
+def tile_of_choice(choice):
+    """The same string for an autotuner choice ({path, atoms_per_tile,
+    network_tile})."""
+    if not choice:
+        return None
+    if choice["path"] == "split":
+        return "%dx%d" % (choice["atoms_per_tile"], choice["network_tile"])
+    return "%d" % choice["atoms_per_tile"]
+
+
 def pmc_summary(fetch_db, write_db, variant, mib, command, workload="cluster2500"):
     """Markdown summary of a FETCH_SIZE run and a WRITE_SIZE run: per-dispatch
     KiB of the evaluation kernel(s), scaled by the calibration kernel's
@@ -393,6 +417,7 @@ def pmc_summary(fetch_db, write_db, variant, mib, command, workload="cluster2500
         "Kernels seen: %s" % ", ".join(fr["names"]),
         "",
         "- variant: %s" % variant,
+        "- tile: %s" % tile_of_kernels(fr["names"]),
         "- hbm_bytes_per_launch: %d" % int(round(fetch_b + write_b)),
         "- fetch_bytes_per_launch: %d" % int(round(fetch_b)),
         "- write_bytes_per_launch: %d" % int(round(write_b)),
@@ -477,15 +502,18 @@ def traffic_summary_path(variant, workload):
     return os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.md" % (kern, dtype, workload))
 
 
-def load_traffic(variant, summary=None):
+def load_traffic(variant, summary=None, tile=None):
     """HBM bytes per launch from the committed counter summary, or None when
-    it covers another variant or the kernel sources changed since."""
+    it covers another variant or tile configuration (tile given), or the
+    kernel sources changed since."""
     try:
         txt = open(summary or TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     kv = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
     if kv.get("variant") != variant or kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if tile is not None and kv.get("tile") != tile:
         return None
     return int(kv["hbm_bytes_per_launch"])
 
@@ -674,7 +702,7 @@ def main():
     valu_tflops = valu_flop / t_eval / 1e12
     mfma_peak = MI355X_FP8_MFMA_TFLOPS if best["dtype"] == "fp8" else MI355X_BF16_MFMA_TFLOPS
     mlp_peak = MI355X_FP32_VECTOR_TFLOPS if best["dtype"] == "fp32" else mfma_peak
-    traffic = load_traffic("%s:%s" % (best["dtype"], best["path"]))
+    traffic = load_traffic("%s:%s" % (best["dtype"], best["path"]), tile=tile_of_choice(best.get("autotune")))
     sol_s = valu_flop / (MI355X_FP32_VECTOR_TFLOPS * 1e12) + mlp_flop / (mlp_peak * 1e12)
     roofline = {
         "bound": "alu", "achieved": valu_tflops, "peak": MI355X_FP32_VECTOR_TFLOPS,

@@ -73,13 +73,15 @@ def test_counter_summary_rates(tmp_path, capsys):
 
 def test_traffic_summary_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
     """The committed traffic summary is used only for its own variant and
-    only while the kernel sources hash as recorded."""
+    tile configuration and only while the kernel sources hash as recorded."""
     txt = open(bench.TRAFFIC_SUMMARY).read()
     kv = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
     current = tmp_path / "current.md"
     current.write_text(txt.replace(kv["kernel_source_sha256"], bench.kernel_source_hash()))
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(current))
     assert bench.load_traffic(kv["variant"]) == int(kv["hbm_bytes_per_launch"])
+    assert bench.load_traffic(kv["variant"], tile=kv.get("tile")) == int(kv["hbm_bytes_per_launch"])
+    assert bench.load_traffic(kv["variant"], tile="999") is None
     assert bench.load_traffic("fp32:plain") is None
     stale = tmp_path / "stale.md"
     stale.write_text(txt.replace(kv["kernel_source_sha256"], "0" * 64))
@@ -99,3 +101,15 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_tile_names():
+    names = ["void nnp::k_eval_pooled<13, 2, true>(nnp::Sys)"]
+    assert bench.tile_of_kernels(names) == "13"
+    split = ["void nnp::k_desc_pooled<5>(nnp::Sys)", "void nnp::k_mlp_wide<2, true, true>(nnp::Sys)",
+             "void nnp::k_adj_pooled<5>(nnp::Sys)"]
+    assert bench.tile_of_kernels(split) == "5x32"
+    assert bench.tile_of_kernels(names + split) is None
+    assert bench.tile_of_choice({"path": "fused", "atoms_per_tile": 13, "network_tile": 64}) == "13"
+    assert bench.tile_of_choice({"path": "split", "atoms_per_tile": 5, "network_tile": 32}) == "5x32"
+    assert bench.tile_of_choice(None) is None
