@@ -43,21 +43,23 @@ def periodic_ref():
     return get
 
 
-@pytest.mark.parametrize("name,dtype,path", [
-    ("box250", "fp32", "fused"), ("box250", "fp32", "plain"), ("box250", "bf16x3", "fused"),
-    ("box2500", "fp32", "fused"), ("box2500", "bf16x3", "fused"),
+@pytest.mark.parametrize("name,dtype,path,T", [
+    ("box250", "fp32", "fused", 0), ("box250", "fp32", "plain", 0), ("box250", "bf16x3", "fused", 0),
+    ("box2500", "fp32", "fused", 0), ("box2500", "bf16x3", "fused", 0),
+    # 14-atom tiles: every atom a full shell, the smallest force-merge table
+    ("box2500", "bf16x3", "fused", 14),
 ])
-def test_periodic_energy_forces_match_oracle(make_system, periodic_ref, name, dtype, path):
+def test_periodic_energy_forces_match_oracle(make_system, periodic_ref, name, dtype, path, T):
     s = make_system(name)
     Eo, Eio, Fo = periodic_ref(s)
-    ctx = _ctx(s, dtype=dtype, path=path)
+    ctx = _ctx(s, dtype=dtype, path=path, atoms_per_tile=T)
     E, F = ctx.compute(s.pos)
     Ei = ctx.atom_energies()
     S = np.abs(Eio).sum()
     dE = abs(E[0] - Eo) / S
     dF = np.abs(F - Fo).max()
     dEi = np.abs(Ei - Eio).max()
-    _say("%s %s %s: |dE|/S %.2e max|dF| %.2e max|dEi| %.2e" % (name, dtype, path, dE, dF, dEi))
+    _say("%s %s %s T=%d: |dE|/S %.2e max|dF| %.2e max|dEi| %.2e" % (name, dtype, path, T, dE, dF, dEi))
     assert dE <= TOL_E[dtype]
     assert dF <= TOL_F[dtype]
     assert dEi <= TOL_EI[dtype]
