@@ -1099,21 +1099,30 @@ __device__ __forceinline__ void table_add_atom_pooled(const Sys& S, const ForceT
     const int lane = lane_id();
     long long sx = 0, sy = 0, sz = 0;
     bool bad = false;
-    for (int e = lane; e < E.nR; e += 64) {
+    // angular entries are the radial entries within the angular cutoff, in
+    // radial order (env_append): entry e is angular entry j = the number of
+    // such entries before it, so each neighbour takes one table add with its
+    // radial and angular parts (integer sums: the same totals)
+    int jbase = 0;
+    for (int e0 = 0; e0 < E.nR; e0 += 64) {  // wave-uniform
+        const int e = e0 + lane;
+        const bool live = e < E.nR;
+        const bool isA = live && E.geo[e].w < kCutAng;
+        const unsigned long long mA = __ballot(isA);
+        const int j = jbase + lanes_below(mA);
+        jbase += __popcll(mA);
+        if (!live) continue;
         long long qx, qy, qz;
         if (!fixed_force(facc, e, qx, qy, qz)) {
             bad = true;
             continue;
         }
+        if (isA && j < E.nA) {
+            qx += (long long)faccA[3 * j];
+            qy += (long long)faccA[3 * j + 1];
+            qz += (long long)faccA[3 * j + 2];
+        }
         table_add(S, t, E.nid[e], qx, qy, qz);
-        sx += qx;
-        sy += qy;
-        sz += qz;
-    }
-    for (int j = lane; j < E.nA; j += 64) {
-        const long long qx = (long long)faccA[3 * j], qy = (long long)faccA[3 * j + 1];
-        const long long qz = (long long)faccA[3 * j + 2];
-        table_add(S, t, E.nid[E.ang[j]], qx, qy, qz);
         sx += qx;
         sy += qy;
         sz += qz;
