@@ -295,8 +295,8 @@ nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
     return upload_tile_mol(c);
 }
 
-// Tiles whose atoms pool their angular work (10 per tile) take as long as
-// their total work.  Between blocks of steps the atoms of each element are
+// Tiles whose atoms pool their angular work take as long as their total
+// work.  Between blocks of steps the atoms of each element are
 // moved between its tiles, heaviest atom of the heaviest tile for the
 // lightest atom of the lightest tile, while that lowers the heavier of the
 // two; the work per atom comes from the last evaluation.  Deterministic (a

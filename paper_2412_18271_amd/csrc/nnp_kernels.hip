@@ -177,14 +177,15 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
 // hundred distinct receiving atoms, and a nearly full table probes long.
 constexpr int kPoolTableExtra = 10240;  // floats
 
-// Workgroup of the pooled kernel: 16 waves for a tile of 10 or 12 atoms; 8
+// Workgroup of the pooled kernel: 16 waves for a tile of 10 to 14 atoms; 8
 // waves for a tile of 5, whose LDS (70 KB) lets two tiles share a CU and
 // overlap their dependent chains of memory, LDS, MFMA and ALU work.  One wave
-// per atom loads the environments; the pooled angular work, the network's
-// output-row tiles and the force merge spread over all the waves.  12-atom
-// tiles fill 12 of the 16 MFMA columns (10 of 16 at 10 atoms) and so stream
-// the weight fragments for 20 % more atoms; their environments leave a
-// smaller force-merge table.
+// per atom loads the environments (and one more plans the angular runs); the
+// pooled angular work, the network's output-row tiles and the force merge
+// spread over all the waves.  A tile streams its element's weight fragments
+// once whatever its atom count, so 12-14 atoms per tile (12-14 of the 16 MFMA
+// columns) share that pass among more atoms than 10; their environments
+// leave less LDS to the force-merge table (T = 14: 163,056 of 163,840 bytes).
 template <int T>
 constexpr int kPoolThreads = T <= 7 ? 512 : 1024;
 template <int T>
@@ -206,6 +207,9 @@ struct PooledSmem {
     } u;
     float E[16];
 };
+static_assert(sizeof(PooledSmem<14, 2>) <= 163840 && sizeof(PooledSmem<13, 2>) <= 163840 &&
+                  sizeof(PooledSmem<12, 2>) <= 163840,
+              "pooled workgroup LDS");
 
 template <int T, int MODE, bool GRAD>
 __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, MODE>& sm)
@@ -1060,8 +1064,8 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
 
 // ------------------------------------------------------------ launchers ---
 
-// Tiles of 10 atoms (one workgroup per CU at 2,500 atoms) pool the angular
-// work; the other tile sizes keep one wave per atom throughout.
+// Tiles of 5 and of 10-14 atoms pool the angular work over the workgroup;
+// the other tile sizes keep one wave per atom throughout.
 template <int T>
 constexpr bool kPooledTile = T == 10 || T == 5 || T == 12 || T == 13 || T == 14;
 
