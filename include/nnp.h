@@ -122,13 +122,15 @@ typedef struct {
     double skin;                 /* pair-list skin in A (e.g. 1.0), >= 0 */
     int32_t max_neighbors;       /* capacity of one atom's pair list (cutoff 5.2 + skin),
                                     <= 256; 0 selects 192 */
-    int32_t atoms_per_tile;      /* atoms per workgroup: 4, 5, 8, 10, 12, 13, 14 or, with
+    int32_t atoms_per_tile;      /* atoms per workgroup: 4, 5, 8, 10, 12 to 15 or, with
                                     the BF16 and split-BF16 networks, 16 (fused path); 8 or
                                     16 (plain path); 4, 5, 7 or 10 (descriptor and adjoint
                                     kernels of the split path); 0 selects 16 (plain), 5
-                                    (split) or, for the fused path, the smallest of 8, 10,
-                                    12, 13 and 14 that gives at most one workgroup per
-                                    compute unit, else 14 */
+                                    (split) or, for the fused path, the smallest of 8, 10
+                                    and 12 to 15 that gives at most one workgroup per
+                                    compute unit, else the one of 10 and 12 to 15 with the
+                                    least modelled time in rounds of one workgroup per
+                                    compute unit */
     void* stream;                /* hipStream_t to run on (see use_stream) */
     int32_t use_stream;          /* nonzero: run on `stream` even when it is NULL (the null
                                     stream, e.g. PyTorch's default stream); zero: a NULL
@@ -327,10 +329,10 @@ nnp_status nnp_device_bytes(nnp_context* ctx, int64_t* bytes);
 /* Times the candidate kernel configurations on the current positions and
  * keeps the fastest:
  *   plain path: atoms per network tile 8 or 16;
- *   fused path, FP32 / FP8 networks: atoms per workgroup 4, 5, 8, 10, 12,
- *     13, 14;
+ *   fused path, FP32 / FP8 networks: atoms per workgroup 4, 5, 8, 10 and
+ *     12 to 15;
  *   fused or split path, BF16 / split-BF16 networks: the fused kernel with
- *     4, 5, 8, 10, 12, 13, 14 or 16 atoms per workgroup, and the split path
+ *     4, 5, 8, 10, 12 to 16 atoms per workgroup, and the split path
  *     with 4, 5, 7 or 10 atoms per descriptor / adjoint workgroup times 32 or
  *     64 atoms per network workgroup (the path may change between fused and
  *     split: same arithmetic, results equal to rounding).

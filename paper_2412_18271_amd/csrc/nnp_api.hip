@@ -227,7 +227,7 @@ nnp_status check_positions(nnp_context* c, const double* pos)
 // Tiles of 16 atoms exceed the LDS of a CU with the FP32 and FP8 networks.
 bool fused_tile_ok(int T, nnp_dtype d)
 {
-    return T == 4 || T == 5 || T == 8 || T == 10 || T == 12 || T == 13 || T == 14 ||
+    return T == 4 || T == 5 || T == 8 || T == 10 || (T >= 12 && T <= 15) ||
            (T == 16 && (d == NNP_MLP_BF16 || d == NNP_MLP_BF16_SPLIT));
 }
 
@@ -549,18 +549,30 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     std::vector<int> elem(n);
     for (int k = 0; k < n; ++k) elem[k] = (int)p4[k].w;
     if (c->T_auto) {
-        // the smallest of 8, 10, 12, 13 and 14 atoms per tile that gives one
-        // workgroup per CU (a second one on a CU runs after the first); larger
-        // systems take 14, whose tiles share each pass over the weight
-        // fragments among the most atoms
+        // the smallest of 8, 10, 12-15 atoms per tile that gives one
+        // workgroup per CU (a second one on a CU runs after the first); for
+        // more tiles than CUs the pooled tile size with the least time in
+        // rounds of one tile per CU, a tile taking ~21 us + ~1 us per atom
+        // (per-workgroup stamps of the 10-14-atom kernels)
         int dev = 0, ncu = 256;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        c->T = 14;
-        for (int T : {8, 10, 12, 13})
+        c->T = 0;
+        for (int T : {8, 10, 12, 13, 14, 15})
             if (make_tiles(elem, T).size() <= (size_t)ncu) {
                 c->T = T;
                 break;
             }
+        if (c->T == 0) {
+            double best = 0.0;
+            for (int T : {10, 12, 13, 14, 15}) {
+                const double rounds = (double)((make_tiles(elem, T).size() + ncu - 1) / ncu);
+                const double cost = rounds * (21.0 + T);
+                if (c->T == 0 || cost < best) {
+                    best = cost;
+                    c->T = T;
+                }
+            }
+        }
     }
     const std::vector<int4> tiles = make_tiles(elem, c->T);
     std::vector<int> perm_dev(c->perm.begin(), c->perm.end());
@@ -958,7 +970,7 @@ static nnp_status validate_params(const nnp_params* p, std::string& msg)
     if (!(p->skin >= 0.0) || !std::isfinite(p->skin) || p->skin > 5.0) return msg = "skin must be in [0, 5] A", NNP_ERR_ARG;
     if (p->max_neighbors < 0 || p->max_neighbors > kCapMax) return msg = "max_neighbors must be in [0, 256]", NNP_ERR_ARG;
     if (p->path == NNP_PATH_FUSED && p->atoms_per_tile != 0 && !fused_tile_ok(p->atoms_per_tile, p->mlp_dtype))
-        return msg = "atoms_per_tile of the fused path must be 0, 4, 5, 8, 10, 12, 13, 14 or (BF16 networks) 16", NNP_ERR_ARG;
+        return msg = "atoms_per_tile of the fused path must be 0, 4, 5, 8, 10, 12-15 or (BF16 networks) 16", NNP_ERR_ARG;
     if (p->path == NNP_PATH_PLAIN && p->atoms_per_tile != 0 && p->atoms_per_tile != 8 && p->atoms_per_tile != 16)
         return msg = "atoms_per_tile of the plain path must be 0, 8 or 16", NNP_ERR_ARG;
     if (p->path == NNP_PATH_SPLIT && p->atoms_per_tile != 0 && !split_tile_ok(p->atoms_per_tile))
@@ -1754,7 +1766,7 @@ nnp_status nnp_autotune(nnp_context* c, const char* cache_path, int32_t* choice)
     if (family == 0) {
         cand = {{NNP_PATH_PLAIN, 8, c->nblk}, {NNP_PATH_PLAIN, 16, c->nblk}};
     } else {
-        for (int T : {4, 5, 8, 10, 12, 13, 14, 16})
+        for (int T : {4, 5, 8, 10, 12, 13, 14, 15, 16})
             if (fused_tile_ok(T, c->dtype)) cand.push_back({NNP_PATH_FUSED, T, c->nblk});
         if (bf)
             for (int T : {4, 5, 7, 10})

@@ -635,24 +635,32 @@ __device__ __forceinline__ void angular_store(const float* acc, float* G)
 // facc[3 * entry] (LDS).  Radial entries are owned by one lane each (plain
 // store); the angular pairs then add with LDS atomics.  The caller separates
 // the two phases with a barrier.
+// Force on radial entry e of the atom from its radial features: g holds
+// the atom's dE/dG radial part (16 values per neighbour element).
+__device__ __forceinline__ float3 radial_force(const Env& E, int e, const float* g)
+{
+    const float4 ge = E.geo[e];
+    const float2 f = E.fcr[e];
+    const float* gs = g + 16 * (E.info[e] & 3);
+    float dEdr = 0.f;
+#pragma unroll
+    for (int k = 0; k < kNumRadial; ++k) {
+        const float x = ge.w - (0.9f + 0.28f * (float)k);
+        const float ex = __expf(-kEtaRad * x * x);
+        dEdr += gs[k] * ex * (f.y - 2.f * kEtaRad * x * f.x);
+    }
+    return make_float3(-dEdr * ge.x, -dEdr * ge.y, -dEdr * ge.z);
+}
+
 __device__ __forceinline__ void adjoint_radial(const Env& E, const float* g, float* facc)
 {
     const int lane = lane_id();
     const int nR = E.nR;
     for (int e = lane; e < nR; e += 64) {
-        const float4 ge = E.geo[e];
-        const float2 f = E.fcr[e];
-        const float* gs = g + 16 * (E.info[e] & 3);
-        float dEdr = 0.f;
-#pragma unroll
-        for (int k = 0; k < kNumRadial; ++k) {
-            const float x = ge.w - (0.9f + 0.28f * (float)k);
-            const float ex = __expf(-kEtaRad * x * x);
-            dEdr += gs[k] * ex * (f.y - 2.f * kEtaRad * x * f.x);
-        }
-        facc[3 * e + 0] = -dEdr * ge.x;
-        facc[3 * e + 1] = -dEdr * ge.y;
-        facc[3 * e + 2] = -dEdr * ge.z;
+        const float3 v = radial_force(E, e, g);
+        facc[3 * e + 0] = v.x;
+        facc[3 * e + 1] = v.y;
+        facc[3 * e + 2] = v.z;
     }
 }
 
@@ -785,14 +793,18 @@ __device__ __forceinline__ void adjoint_angular(const Env& E, const float* g, fl
 
 // Fixed-point force of one neighbour entry (kFixScale units), or false when
 // a component is not finite or beyond kFixMax.
-__device__ __forceinline__ bool fixed_force(const float* facc, int e, long long& qx, long long& qy, long long& qz)
+__device__ __forceinline__ bool fixed_vec(float fx, float fy, float fz, long long& qx, long long& qy, long long& qz)
 {
-    const float fx = facc[3 * e], fy = facc[3 * e + 1], fz = facc[3 * e + 2];
     if (!(fabsf(fx) < kFixMax && fabsf(fy) < kFixMax && fabsf(fz) < kFixMax)) return false;
     qx = __double2ll_rn((double)fx * kFixScale);
     qy = __double2ll_rn((double)fy * kFixScale);
     qz = __double2ll_rn((double)fz * kFixScale);
     return true;
+}
+
+__device__ __forceinline__ bool fixed_force(const float* facc, int e, long long& qx, long long& qy, long long& qz)
+{
+    return fixed_vec(facc[3 * e], facc[3 * e + 1], facc[3 * e + 2], qx, qy, qz);
 }
 
 __device__ __forceinline__ void global_force_add(const Sys& S, int j, long long qx, long long qy, long long qz)
@@ -1091,10 +1103,11 @@ __device__ __forceinline__ void adjoint_angular_pooled(const Sys& S, const Env* 
     if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&S.st->nonfinite, 1);
 }
 
-// Forces of E_a for the wave's atom a from its radial part (facc, float) and
-// its pooled angular part (faccA, fixed point), merged in the table.
+// Forces of E_a for the wave's atom a, merged in the table: the radial part
+// computed here from g (the atom's 64 radial dE/dG values), the pooled
+// angular part from faccA (fixed point).
 __device__ __forceinline__ void table_add_atom_pooled(const Sys& S, const ForceTable& t, int a, const Env& E,
-                                                      const float* facc, const unsigned long long* faccA)
+                                                      const float* g, const unsigned long long* faccA)
 {
     const int lane = lane_id();
     long long sx = 0, sy = 0, sz = 0;
@@ -1113,7 +1126,8 @@ __device__ __forceinline__ void table_add_atom_pooled(const Sys& S, const ForceT
         jbase += __popcll(mA);
         if (!live) continue;
         long long qx, qy, qz;
-        if (!fixed_force(facc, e, qx, qy, qz)) {
+        const float3 v = radial_force(E, e, g);
+        if (!fixed_vec(v.x, v.y, v.z, qx, qy, qz)) {
             bad = true;
             continue;
         }

@@ -188,27 +188,41 @@ constexpr int kPoolTableExtra = 10240;  // floats
 // leave less LDS to the force-merge table (T = 14: 163,056 of 163,840 bytes).
 template <int T>
 constexpr int kPoolThreads = T <= 7 ? 512 : 1024;
-template <int T>
-constexpr int kPoolTableFloats = T <= 7 ? 3072 : T <= 10 ? kPoolTableExtra : T == 12 ? 6016 : T == 13 ? 3200 : 256;
+
+template <int T, int MODE>
+union __attribute__((aligned(16))) PooledUnion {  // 16-byte LDS vector accesses
+    typename MlpSmemOf<T, MODE>::type m;
+    unsigned long long accI[T * 320];  // angular features (descriptor phase)
+    struct {
+        float gr[T * 64];                            // radial dE/dG of each atom
+        unsigned long long faccA[T * kAngMax * 3];   // angular part of the forces (fixed point)
+    } adj;
+};
+
+// LDS of a workgroup (160 KiB on gfx950) and the force-merge table's floats
+// beyond G: up to 10 atoms a fixed 10,240 (one workgroup per CU; a larger
+// table clears and flushes longer), 3,072 for two workgroups of 5 atoms per
+// CU, and for 12-14 atoms whatever the other buffers leave.
+constexpr size_t kLdsBytes = 163840;
+template <int T, int MODE>
+constexpr int kPoolTableFloats =
+    T <= 7 ? 3072
+    : T <= 10
+        ? kPoolTableExtra
+        : (int)((kLdsBytes - sizeof(Env) * T - sizeof(float) * T * kLdG - sizeof(PoolPlan<T>) -
+                 sizeof(PooledUnion<T, MODE>) - 16 * sizeof(float) - 64) / sizeof(float)) & ~63;
 
 template <int T, int MODE>
 struct PooledSmem {
     Env env[T];
     float G[T * kLdG];
-    float Gx[kPoolTableFloats<T>];  // continues G for the force-merge table only
+    float Gx[kPoolTableFloats<T, MODE>];  // continues G for the force-merge table only
     PoolPlan<T> plan;
-    union __attribute__((aligned(16))) {  // 16-byte LDS vector accesses
-        typename MlpSmemOf<T, MODE>::type m;
-        unsigned long long accI[T * 320];  // angular features (descriptor phase)
-        struct {
-            float facc[T * 3 * kRadMax];                 // radial part of the forces
-            unsigned long long faccA[T * kAngMax * 3];   // angular part (fixed point)
-        } adj;
-    } u;
+    PooledUnion<T, MODE> u;
     float E[16];
 };
-static_assert(sizeof(PooledSmem<14, 2>) <= 163840 && sizeof(PooledSmem<13, 2>) <= 163840 &&
-                  sizeof(PooledSmem<12, 2>) <= 163840,
+static_assert(sizeof(PooledSmem<15, 0>) <= kLdsBytes && sizeof(PooledSmem<15, 2>) <= kLdsBytes &&
+                  sizeof(PooledSmem<15, 3>) <= kLdsBytes && sizeof(PooledSmem<12, 2>) <= kLdsBytes,
               "pooled workgroup LDS");
 
 template <int T, int MODE, bool GRAD>
@@ -269,8 +283,9 @@ __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, 
     if (act && lane == 0) S.Ei[a] = sm.E[wave];
     if (GRAD) {
         for (int i = tid; i < T * kAngMax * 3; i += NT) sm.u.adj.faccA[i] = 0ull;
-        float* fa = sm.u.adj.facc + w * 3 * kRadMax;
-        if (act) adjoint_radial(E, Grow, fa);
+        // each atom's radial dE/dG leaves G before the merge table covers it;
+        // the radial forces are computed in the merge itself
+        for (int i = tid; i < T * 64; i += NT) sm.u.adj.gr[i] = sm.G[(i >> 6) * kLdG + (i & 63)];
         __syncthreads();
         adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.u.adj.faccA, tid);
         __syncthreads();
@@ -279,7 +294,8 @@ __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, 
         const ForceTable ft = force_table(sm.G, sizeof(sm.G) + sizeof(sm.Gx));
         table_clear(ft, tid, NT);
         __syncthreads();
-        if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.u.adj.faccA + (size_t)wave * kAngMax * 3);
+        if (act)
+            table_add_atom_pooled(S, ft, a, E, sm.u.adj.gr + w * 64, sm.u.adj.faccA + (size_t)wave * kAngMax * 3);
         __syncthreads();
         table_flush(S, ft, tid, NT);
     }
@@ -383,15 +399,15 @@ template <int T>
 struct AdjSmem {
     float G[T * kLdG];               // dE/dG rows, then (with Gx) the force-merge table
     float Gx[kSplitTableExtra<T>];
-    float facc[T * 3 * kRadMax];                 // radial part of the forces
-    unsigned long long faccA[T * kAngMax * 3];   // angular part (fixed point)
+    float gr[T * 64];                            // radial dE/dG of each atom
+    unsigned long long faccA[T * kAngMax * 3];   // angular part of the forces (fixed point)
     Env env[T];
     PoolPlan<T> plan;
 };
 
 // Third kernel: environments from the lists the first kernel left, dE/dG
-// rows from S.dG, radial and pooled angular adjoint, force merge, HBM
-// fixed-point sums.
+// rows from S.dG, pooled angular adjoint, force merge (the radial forces
+// computed there), HBM fixed-point sums.
 template <int T>
 __device__ __forceinline__ void adj_tile(const Sys& S, int tb, AdjSmem<T>& sm)
 {
@@ -411,17 +427,19 @@ __device__ __forceinline__ void adj_tile(const Sys& S, int tb, AdjSmem<T>& sm)
                 *reinterpret_cast<const float4*>(S.dG + (size_t)col[t] * kNumFeat + f);
     }
     for (int i = tid; i < T * kAngMax * 3; i += NT) sm.faccA[i] = 0ull;
+    for (int i = tid; i < T * 64; i += NT) {
+        const int t = i >> 6;
+        sm.gr[i] = t < tile.y ? S.dG[(size_t)col[t] * kNumFeat + (i & 63)] : 0.f;
+    }
     __syncthreads();
     if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
-    float* fa = sm.facc + w * 3 * kRadMax;
-    if (act) adjoint_radial(E, sm.G + w * kLdG, fa);
     __syncthreads();
     adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.faccA, tid);
     __syncthreads();
     const ForceTable ft = force_table(sm.G, sizeof(sm.G) + sizeof(sm.Gx));
     table_clear(ft, tid, NT);
     __syncthreads();
-    if (act) table_add_atom_pooled(S, ft, a, E, fa, sm.faccA + (size_t)wave * kAngMax * 3);
+    if (act) table_add_atom_pooled(S, ft, a, E, sm.gr + w * 64, sm.faccA + (size_t)wave * kAngMax * 3);
     __syncthreads();
     table_flush(S, ft, tid, NT);
 }
@@ -1067,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
 // Tiles of 5 and of 10-14 atoms pool the angular work over the workgroup;
 // the other tile sizes keep one wave per atom throughout.
 template <int T>
-constexpr bool kPooledTile = T == 10 || T == 5 || T == 12 || T == 13 || T == 14;
+constexpr bool kPooledTile = T == 5 || (T >= 10 && T <= 15 && T != 11);
 
 template <int T, int MODE, bool GRAD>
 static hipError_t launch_fused_t(const Sys& S, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
@@ -1118,6 +1136,7 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(12, 0)
         NNP_FUSED(13, 0)
         NNP_FUSED(14, 0)
+        NNP_FUSED(15, 0)
         NNP_FUSED(4, 1)
         NNP_FUSED(5, 1)
         NNP_FUSED(8, 1)
@@ -1125,6 +1144,7 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(12, 1)
         NNP_FUSED(13, 1)
         NNP_FUSED(14, 1)
+        NNP_FUSED(15, 1)
         NNP_FUSED(16, 1)
         NNP_FUSED(4, 2)
         NNP_FUSED(5, 2)
@@ -1133,6 +1153,7 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(12, 2)
         NNP_FUSED(13, 2)
         NNP_FUSED(14, 2)
+        NNP_FUSED(15, 2)
         NNP_FUSED(16, 2)
         NNP_FUSED(4, 3)
         NNP_FUSED(5, 3)
@@ -1141,6 +1162,7 @@ hipError_t launch_eval(const Sys& S, int path, int mode, int T, bool grad, hipSt
         NNP_FUSED(12, 3)
         NNP_FUSED(13, 3)
         NNP_FUSED(14, 3)
+        NNP_FUSED(15, 3)
 #undef NNP_FUSED
         return hipErrorInvalidValue;
     }

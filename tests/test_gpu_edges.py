@@ -123,7 +123,7 @@ def test_batch_of_tiny_and_ragged_molecules(weights, dtype, path):
     ctx.close()
 
 
-@pytest.mark.parametrize("T", [0, 5, 10, 12, 14])
+@pytest.mark.parametrize("T", [0, 5, 10, 12, 14, 15])
 def test_capacity_overflow_is_an_error(weights, T):
     """200 atoms packed into a 3 A ball: every atom has ~199 neighbours within
     5.2 A, beyond the 160 radial entries held per atom and the pair-list

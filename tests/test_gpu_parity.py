@@ -76,12 +76,12 @@ def test_descriptors_match_oracle(make_system):
 
 @pytest.mark.parametrize("path,dtype,T", [("plain", "fp32", 16), ("plain", "fp32", 8), ("fused", "fp32", 8),
                                           ("fused", "fp32", 4), ("fused", "fp32", 5), ("fused", "fp32", 10),
-                                          ("fused", "fp32", 12), ("fused", "fp32", 14),
+                                          ("fused", "fp32", 12), ("fused", "fp32", 15),
                                           ("plain", "bf16", 16), ("fused", "bf16", 8), ("fused", "bf16", 4),
                                           ("fused", "bf16", 5), ("fused", "bf16", 10), ("fused", "bf16", 12), ("plain", "bf16x3", 16),
                                           ("fused", "bf16x3", 8), ("fused", "bf16x3", 4), ("fused", "bf16x3", 5),
                                           ("fused", "bf16x3", 10), ("fused", "bf16x3", 12), ("fused", "bf16x3", 13),
-                                          ("fused", "bf16x3", 14), ("fused", "bf16x3", 16),
+                                          ("fused", "bf16x3", 14), ("fused", "bf16x3", 15), ("fused", "bf16x3", 16),
                                           ("fused", "bf16x3", 0)])
 @pytest.mark.parametrize("name", ["mol22", "cluster2500"])
 def test_energy_forces_match_oracle(oracle_cache, name, path, dtype, T):
