@@ -391,6 +391,9 @@ nnp_status rebalance_tiles(nnp_context* c)
 nnp_status setup_grids(nnp_context* c, const double* pos)
 {
     Sys& S = c->S;
+    // the grid arrays below are rewritten from the host: nothing of this
+    // context may still be reading them
+    if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
     std::vector<int> molgrid(c->nmol, -1);
     std::vector<CellGrid> grids;
     long long ncells = 0;
@@ -474,8 +477,12 @@ nnp_status setup_grids(nnp_context* c, const double* pos)
         c->cell_cap = ncells;
     }
     S.ncells = (int)ncells;
-    if (ncells > 0)
+    if (ncells > 0) {
         HIP_TRY(c, hipMemcpy((void*)S.grids, grids.data(), sizeof(CellGrid) * grids.size(), hipMemcpyHostToDevice));
+        // the cell scan clears what it reads; a new layout starts from zero
+        HIP_TRY(c, hipMemset(S.cell_count, 0, sizeof(int) * ncells));
+        HIP_TRY(c, hipMemset(S.cell_fill, 0, sizeof(int) * ncells));
+    }
     c->molgrid = molgrid;
     return upload_tile_mol(c);
 }

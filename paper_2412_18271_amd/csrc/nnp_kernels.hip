@@ -898,15 +898,6 @@ __device__ __forceinline__ int cell_coord(double x, double o, double inv_h, int 
     return f < 0.0 ? 0 : (f >= (double)n ? n - 1 : (int)f);
 }
 
-__global__ __launch_bounds__(256) void k_cell_zero(Sys S)
-{
-    if (!rebuild_due(S.st, S.rebuild_every)) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.ncells; i += gridDim.x * blockDim.x) {
-        S.cell_count[i] = 0;
-        S.cell_fill[i] = 0;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_cell_count(Sys S)
 {
     if (!rebuild_due(S.st, S.rebuild_every)) return;
@@ -927,7 +918,10 @@ __global__ __launch_bounds__(256) void k_cell_count(Sys S)
     atomicAdd(&S.cell_count[c], 1);
 }
 
-// Exclusive scan of the cell counts (one workgroup of 1024 threads).
+// Exclusive scan of the cell counts (one workgroup of 1024 threads).  The
+// counts and fill counters are cleared once read, ready for the fill below
+// and the next rebuild's count (the host zeroes them when it lays out the
+// grids).
 __global__ __launch_bounds__(1024) void k_cell_scan(Sys S)
 {
     if (!rebuild_due(S.st, S.rebuild_every)) return;
@@ -949,6 +943,8 @@ __global__ __launch_bounds__(1024) void k_cell_scan(Sys S)
     for (int i = lo; i < hi; ++i) {
         S.cell_start[i] = run;
         run += S.cell_count[i];
+        S.cell_count[i] = 0;
+        S.cell_fill[i] = 0;
     }
     if (t == 1023) S.cell_start[nc] = part[1023];
 }
@@ -964,13 +960,14 @@ __global__ __launch_bounds__(256) void k_cell_fill(Sys S)
     S.cell_atoms[S.cell_start[c] + slot] = a;
 }
 
-// Sorts 256 keys in LDS ascending (one wave, bitonic network).
-__device__ void wave_sort256(int* keys)
+// Sorts the first n keys in LDS ascending (one wave, bitonic network; n a
+// power of two, 64 <= n <= 256, wave-uniform).
+__device__ void wave_sort(int* keys, int n)
 {
     const int lane = lane_id();
-    for (int k = 2; k <= kCapMax; k <<= 1) {
+    for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < kCapMax; i += 64) {
+            for (int i = lane; i < n; i += 64) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
                     const int x = keys[i], y = keys[ixj];
@@ -1067,9 +1064,12 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
         }
     }
     const int kept = count < kCapMax ? count : kCapMax;
-    for (int i = kept + lane; i < kCapMax; i += 64) K[i] = 0x7fffffff;
+    // the smallest power of two >= kept (at least 64) holds all kept keys;
+    // the padding sorts last
+    const int ns = kept <= 64 ? 64 : kept <= 128 ? 128 : kCapMax;
+    for (int i = kept + lane; i < ns; i += 64) K[i] = 0x7fffffff;
     wave_sync();
-    wave_sort256(K);
+    wave_sort(K, ns);
     const int nS = count < S.cap ? count : S.cap;
     const size_t base = (size_t)a * S.cap;
     for (int i = lane; i < nS; i += 64) S.nbr[base + i] = K[i];
@@ -1111,8 +1111,7 @@ static hipError_t launch_cells(const Sys& S, hipStream_t s, hipEvent_t ev0)
 {
     if (S.ncells <= 0) return hipSuccess;
     const int nb = (S.n + 255) / 256;
-    hipExtLaunchKernelGGL(k_cell_zero, dim3(min((S.ncells + 255) / 256, 1024)), dim3(256), 0, s, ev0, nullptr, 0, S);
-    hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, S);
+    hipExtLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, ev0, nullptr, 0, S);
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, S);
     hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, s, S);
     hipLaunchKernelGGL(k_cell_lists, dim3((S.n + 3) / 4), dim3(256), 0, s, S);
