@@ -960,6 +960,81 @@ __global__ __launch_bounds__(256) void k_cell_fill(Sys S)
     S.cell_atoms[S.cell_start[c] + slot] = a;
 }
 
+// Count, scan and fill of a rebuild in one workgroup when the grids' cells
+// fit its LDS and every thread can hold its atoms' cells in registers (at
+// most 32 each): the counts live in LDS and become the cells' running fill
+// positions after the scan; only cell_start and cell_atoms go to memory (one
+// launch per step instead of three, no zeroing pass).
+constexpr int kCellBuildCells = 16384;
+constexpr int kCellBuildAtoms = 32768;
+
+__global__ __launch_bounds__(1024) void k_cell_build(Sys S)
+{
+    if (!rebuild_due(S.st, S.rebuild_every)) return;
+    __shared__ int cnt[kCellBuildCells];
+    __shared__ int part[1024];
+    const int t = threadIdx.x, nc = S.ncells, n = S.n;
+    for (int i = t; i < nc; i += 1024) cnt[i] = 0;
+    __syncthreads();
+    // atom r * 1024 + t is this thread's r-th; its cell stays in cl[r] (-1:
+    // absent, or its molecule has no grid).  The molecules and then their
+    // grids of all R atoms are requested at once, the positions U at a time.
+    constexpr int R = kCellBuildAtoms / 1024, U = 4;
+    int cl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int a = r * 1024 + t;
+        cl[r] = a < n ? S.mol[a] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) cl[r] = cl[r] >= 0 ? S.molgrid[cl[r]] : -1;
+#pragma unroll
+    for (int r0 = 0; r0 < R; r0 += U) {
+        double4 p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            p[u] = cl[r0 + u] >= 0 ? S.pos[(r0 + u) * 1024 + t] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = cl[r0 + u];
+            if (g < 0) continue;
+            const CellGrid G = S.grids[g];
+            const int c = G.first +
+                          (cell_coord(p[u].z, G.oz, G.ihz, G.nz, G.periodic) * G.ny +
+                           cell_coord(p[u].y, G.oy, G.ihy, G.ny, G.periodic)) *
+                              G.nx +
+                          cell_coord(p[u].x, G.ox, G.ihx, G.nx, G.periodic);
+            cl[r0 + u] = c;
+            atomicAdd(&cnt[c], 1);
+        }
+    }
+    __syncthreads();
+    const int per = (nc + 1023) / 1024;
+    const int lo = min(t * per, nc), hi = min(lo + per, nc);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        const int k = cnt[i];
+        cnt[i] = run;
+        S.cell_start[i] = run;
+        run += k;
+    }
+    if (t == 1023) S.cell_start[nc] = part[1023];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (cl[r] >= 0) S.cell_atoms[atomicAdd(&cnt[cl[r]], 1)] = r * 1024 + t;
+}
+
 // Sorts the first n keys in LDS ascending (one wave, bitonic network; n a
 // power of two, 64 <= n <= 256, wave-uniform).
 __device__ void wave_sort(int* keys, int n)
@@ -1111,9 +1186,13 @@ static hipError_t launch_cells(const Sys& S, hipStream_t s, hipEvent_t ev0)
 {
     if (S.ncells <= 0) return hipSuccess;
     const int nb = (S.n + 255) / 256;
-    hipExtLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, ev0, nullptr, 0, S);
-    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, S);
-    hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, s, S);
+    if (S.ncells <= kCellBuildCells && S.n <= kCellBuildAtoms) {
+        hipExtLaunchKernelGGL(k_cell_build, dim3(1), dim3(1024), 0, s, ev0, nullptr, 0, S);
+    } else {
+        hipExtLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, ev0, nullptr, 0, S);
+        hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, S);
+        hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, s, S);
+    }
     hipLaunchKernelGGL(k_cell_lists, dim3((S.n + 3) / 4), dim3(256), 0, s, S);
     return hipGetLastError();
 }
