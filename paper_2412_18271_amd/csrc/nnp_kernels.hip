@@ -177,15 +177,15 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
 // hundred distinct receiving atoms, and a nearly full table probes long.
 constexpr int kPoolTableExtra = 10240;  // floats
 
-// Workgroup of the pooled kernel: 16 waves for a tile of 10 to 14 atoms; 8
-// waves for a tile of 5, whose LDS (70 KB) lets two tiles share a CU and
+// Workgroup of the pooled kernel: 16 waves for a tile of 10 to 15 atoms; 8
+// waves for a tile of 5, whose LDS (64 KB) lets two tiles share a CU and
 // overlap their dependent chains of memory, LDS, MFMA and ALU work.  One wave
 // per atom loads the environments (and one more plans the angular runs); the
 // pooled angular work, the network's output-row tiles and the force merge
 // spread over all the waves.  A tile streams its element's weight fragments
-// once whatever its atom count, so 12-14 atoms per tile (12-14 of the 16 MFMA
+// once whatever its atom count, so 12-15 atoms per tile (12-15 of the 16 MFMA
 // columns) share that pass among more atoms than 10; their environments
-// leave less LDS to the force-merge table (T = 14: 163,056 of 163,840 bytes).
+// leave less LDS to the force-merge table (T = 15: 163,744 of 163,840 bytes).
 template <int T>
 constexpr int kPoolThreads = T <= 7 ? 512 : 1024;
 
@@ -202,7 +202,7 @@ union __attribute__((aligned(16))) PooledUnion {  // 16-byte LDS vector accesses
 // LDS of a workgroup (160 KiB on gfx950) and the force-merge table's floats
 // beyond G: up to 10 atoms a fixed 10,240 (one workgroup per CU; a larger
 // table clears and flushes longer), 3,072 for two workgroups of 5 atoms per
-// CU, and for 12-14 atoms whatever the other buffers leave.
+// CU, and for 12-15 atoms whatever the other buffers leave.
 constexpr size_t kLdsBytes = 163840;
 template <int T, int MODE>
 constexpr int kPoolTableFloats =
