@@ -127,10 +127,10 @@ typedef struct {
                                     16 (plain path); 4, 5, 7 or 10 (descriptor and adjoint
                                     kernels of the split path); 0 selects 16 (plain), 5
                                     (split) or, for the fused path, the smallest of 8, 10
-                                    and 12 to 15 that gives at most one workgroup per
-                                    compute unit, else the one of 10 and 12 to 15 with the
-                                    least modelled time in rounds of one workgroup per
-                                    compute unit */
+                                    and 12 to 15 (16 with the BF16 networks) that gives at
+                                    most one workgroup per compute unit, else the one of 10
+                                    and 12 to 15 (16) with the least modelled time in
+                                    rounds of one workgroup per compute unit */
     void* stream;                /* hipStream_t to run on (see use_stream) */
     int32_t use_stream;          /* nonzero: run on `stream` even when it is NULL (the null
                                     stream, e.g. PyTorch's default stream); zero: a NULL

@@ -303,7 +303,7 @@ nnp_status upload_tiles(nnp_context* c, const std::vector<int4>& tiles)
 // function of the recorded work).  Synchronises the context stream.
 bool balanced_tiles(const nnp_context* c)
 {
-    return (c->path == NNP_PATH_FUSED && (c->T == 5 || c->T >= 10) && c->T != 16) || c->path == NNP_PATH_SPLIT;
+    return (c->path == NNP_PATH_FUSED && (c->T == 5 || c->T >= 10)) || c->path == NNP_PATH_SPLIT;
 }
 
 nnp_status rebalance_tiles(nnp_context* c)
@@ -556,22 +556,24 @@ nnp_status lay_out(nnp_context* c, const double* pos)
     std::vector<int> elem(n);
     for (int k = 0; k < n; ++k) elem[k] = (int)p4[k].w;
     if (c->T_auto) {
-        // the smallest of 8, 10, 12-15 atoms per tile that gives one
-        // workgroup per CU (a second one on a CU runs after the first); for
-        // more tiles than CUs the pooled tile size with the least time in
-        // rounds of one tile per CU, a tile taking ~21 us + ~1 us per atom
-        // (per-workgroup stamps of the 10-14-atom kernels)
+        // the smallest of 8, 10, 12-15 (and 16 with the BF16 networks) atoms
+        // per tile that gives one workgroup per CU (a second one on a CU runs
+        // after the first); for more tiles than CUs the pooled tile size with
+        // the least time in rounds of one tile per CU, a tile taking ~21 us +
+        // ~1 us per atom (per-workgroup stamps of the 10-14-atom kernels)
+        const int Tmax = fused_tile_ok(16, c->dtype) ? 16 : 15;
         int dev = 0, ncu = 256;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         c->T = 0;
-        for (int T : {8, 10, 12, 13, 14, 15})
-            if (make_tiles(elem, T).size() <= (size_t)ncu) {
+        for (int T : {8, 10, 12, 13, 14, 15, 16})
+            if (T <= Tmax && make_tiles(elem, T).size() <= (size_t)ncu) {
                 c->T = T;
                 break;
             }
         if (c->T == 0) {
             double best = 0.0;
-            for (int T : {10, 12, 13, 14, 15}) {
+            for (int T : {10, 12, 13, 14, 15, 16}) {
+                if (T > Tmax) break;
                 const double rounds = (double)((make_tiles(elem, T).size() + ncu - 1) / ncu);
                 const double cost = rounds * (21.0 + T);
                 if (c->T == 0 || cost < best) {

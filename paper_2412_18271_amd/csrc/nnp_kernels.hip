@@ -177,13 +177,14 @@ __global__ __launch_bounds__(256) void k_descriptors(Sys S)
 // hundred distinct receiving atoms, and a nearly full table probes long.
 constexpr int kPoolTableExtra = 10240;  // floats
 
-// Workgroup of the pooled kernel: 16 waves for a tile of 10 to 15 atoms; 8
-// waves for a tile of 5, whose LDS (64 KB) lets two tiles share a CU and
-// overlap their dependent chains of memory, LDS, MFMA and ALU work.  One wave
-// per atom loads the environments (and one more plans the angular runs); the
-// pooled angular work, the network's output-row tiles and the force merge
-// spread over all the waves.  A tile streams its element's weight fragments
-// once whatever its atom count, so 12-15 atoms per tile (12-15 of the 16 MFMA
+// Workgroup of the pooled kernel: 16 waves for a tile of 10 to 16 atoms (16
+// with the BF16 networks only: the FP32 and FP8 network buffers leave no
+// room); 8 waves for a tile of 5, whose LDS (64 KB) lets two tiles share a
+// CU and overlap their dependent chains of memory, LDS, MFMA and ALU work.
+// One wave per atom loads the environments and the last wave plans the
+// angular runs; the pooled angular work, the network's output-row tiles and
+// the force merge spread over all the waves.  A tile streams its element's weight fragments
+// once whatever its atom count, so 12-16 atoms per tile (12-16 of the 16 MFMA
 // columns) share that pass among more atoms than 10; their environments
 // leave less LDS to the force-merge table (T = 15: 163,744 of 163,840 bytes).
 template <int T>
@@ -202,7 +203,7 @@ union __attribute__((aligned(16))) PooledUnion {  // 16-byte LDS vector accesses
 // LDS of a workgroup (160 KiB on gfx950) and the force-merge table's floats
 // beyond G: up to 10 atoms a fixed 10,240 (one workgroup per CU; a larger
 // table clears and flushes longer), 3,072 for two workgroups of 5 atoms per
-// CU, and for 12-15 atoms whatever the other buffers leave.
+// CU, and for 12-16 atoms whatever the other buffers leave.
 constexpr size_t kLdsBytes = 163840;
 template <int T, int MODE>
 constexpr int kPoolTableFloats =
@@ -222,14 +223,15 @@ struct PooledSmem {
     float E[16];
 };
 static_assert(sizeof(PooledSmem<15, 0>) <= kLdsBytes && sizeof(PooledSmem<15, 2>) <= kLdsBytes &&
-                  sizeof(PooledSmem<15, 3>) <= kLdsBytes && sizeof(PooledSmem<12, 2>) <= kLdsBytes,
+                  sizeof(PooledSmem<15, 3>) <= kLdsBytes && sizeof(PooledSmem<16, 2>) <= kLdsBytes &&
+                  sizeof(PooledSmem<16, 1>) <= kLdsBytes && sizeof(PooledSmem<12, 2>) <= kLdsBytes,
               "pooled workgroup LDS");
 
 template <int T, int MODE, bool GRAD>
 __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, MODE>& sm)
 {
     constexpr int NT = kPoolThreads<T>;
-    static_assert(NT > 64 * T, "a wave per atom and a planning wave");
+    static_assert(NT >= 64 * T, "a wave per atom");
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 tile = S.tiles[tb];
     const bool act = wave < tile.y;  // tile.y <= T
@@ -269,8 +271,8 @@ __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, 
     for (int i = tid; i < T * kLdG; i += NT) sm.G[i] = 0.f;
     for (int i = tid; i < T * 320; i += NT) sm.u.accI[i] = 0ull;
     __syncthreads();
-    // the last wave (never an atom's: NT > 64 T) plans the pooled runs while
-    // the atoms' waves compute their radial features
+    // the last wave plans the pooled runs while the atoms' waves compute
+    // their radial features (a 16-atom tile's last wave does both)
     if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
     if (act) radial_features(E, Grow);
     __syncthreads();
@@ -1160,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_cell_lists(Sys S)
 // Tiles of 5 and of 10-14 atoms pool the angular work over the workgroup;
 // the other tile sizes keep one wave per atom throughout.
 template <int T>
-constexpr bool kPooledTile = T == 5 || (T >= 10 && T <= 15 && T != 11);
+constexpr bool kPooledTile = T == 5 || (T >= 10 && T <= 16 && T != 11);
 
 template <int T, int MODE, bool GRAD>
 static hipError_t launch_fused_t(const Sys& S, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)

@@ -57,7 +57,7 @@ def test_autograd_modes_agree_and_scale(make_system):
     two molecules' energies scales each molecule's gradient.
 
     With 8-atom tiles both modes sum each atom's descriptors in the same
-    order and agree to 1e-9.  The default tiles of a system this size (14
+    order and agree to 1e-9.  The default tiles of a system this size (16
     atoms, angular work pooled over the workgroup) sum the angular
     descriptors in fixed point instead: rounding-level differences, bounded
     by twice the split-BF16 force error against the oracle (3e-5 eV/A)."""
