@@ -315,6 +315,13 @@ nnp_status nnp_energy_log(nnp_context* ctx, int32_t count, double* U, double* K,
  * NNP_ERR_STATE).  stats is int64[7]. */
 nnp_status nnp_stats(nnp_context* ctx, int64_t* stats);
 
+/* The kernel configuration in use: config[0] path (nnp_path), [1] atoms per
+ * tile, [2] atoms per network tile of the split path.  With atoms_per_tile
+ * 0 the fused path's tile size is chosen when the positions are first set
+ * (see nnp_params.atoms_per_tile); nnp_autotune may change all three.
+ * config is int32[3].  No device work. */
+nnp_status nnp_get_config(const nnp_context* ctx, int32_t* config);
+
 /* Descriptors at the given host positions, for parity checks: G is host
  * [n_atoms][384] float, caller order.  Synchronises. */
 nnp_status nnp_debug_descriptors(nnp_context* ctx, const double* pos, float* G);

@@ -22,7 +22,7 @@ RETURN_MODES = {"energy_forces": 3, "energy": 1}
 #: Every function the header declares.
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_compute", "nnp_compute_device", "nnp_energy_device",
            "nnp_forces_device", "nnp_energy_device_static", "nnp_set_state",
-           "nnp_get_state", "nnp_step", "nnp_capture", "nnp_energy_log", "nnp_stats", "nnp_debug_descriptors",
+           "nnp_get_state", "nnp_step", "nnp_capture", "nnp_energy_log", "nnp_stats", "nnp_get_config", "nnp_debug_descriptors",
            "nnp_debug_atom_energies", "nnp_device_bytes", "nnp_autotune", "nnp_time_kernels", "nnp_time_steps",
            "nnp_set_thermostat", "nnp_set_box", "nnp_add_force", "nnp_clear_forces",
            "nnp_debug_fp8_encode",
@@ -107,6 +107,7 @@ def load():
         "nnp_capture": (st, [vp, d, i32]),
         "nnp_energy_log": (st, [vp, i32, P(d), P(d), P(i32)]),
         "nnp_stats": (st, [vp, P(i64)]),
+        "nnp_get_config": (st, [vp, P(i32)]),
         "nnp_debug_descriptors": (st, [vp, P(d), P(ctypes.c_float)]),
         "nnp_debug_atom_energies": (st, [vp, P(d)]),
         "nnp_device_bytes": (st, [vp, P(i64)]),

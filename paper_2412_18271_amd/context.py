@@ -242,6 +242,13 @@ class Context:
         return {"evaluations": s[0], "rebuilds": s[1], "forced_rebuilds": s[2], "steps": s[3],
                 "max_pairlist": s[4], "max_radial": s[5], "max_angular": s[6]}
 
+    def config(self):
+        """The kernel configuration in use: {path, atoms_per_tile, network_tile}."""
+        c = (ctypes.c_int32 * 3)()
+        self._check(self._lib.nnp_get_config(self._h, c))
+        names = {v: k for k, v in _lib.PATHS.items()}
+        return {"path": names.get(c[0], c[0]), "atoms_per_tile": int(c[1]), "network_tile": int(c[2])}
+
     def descriptors(self, pos):
         p = self._pos(pos)
         G = np.zeros((self.n_atoms, 384), np.float32)

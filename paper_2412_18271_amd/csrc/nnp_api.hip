@@ -1565,6 +1565,15 @@ nnp_status nnp_stats(nnp_context* c, int64_t* stats)
     return NNP_OK;
 }
 
+nnp_status nnp_get_config(const nnp_context* c, int32_t* config)
+{
+    if (!c || !config) return NNP_ERR_ARG;
+    config[0] = (int32_t)c->path;
+    config[1] = c->T;
+    config[2] = 16 * c->nblk;
+    return NNP_OK;
+}
+
 nnp_status nnp_debug_descriptors(nnp_context* c, const double* pos, float* G)
 {
     if (!c || !pos || !G) return fail(c, NNP_ERR_ARG, "bad arguments");

@@ -88,6 +88,8 @@ int main(void)
     expect(nnp_set_state(NULL, pos, NULL) == NNP_ERR_ARG, "set_state null");
     expect(nnp_get_state(NULL, pos, NULL, NULL, NULL, NULL) == NNP_ERR_ARG, "get_state null");
     expect(nnp_autotune(NULL, NULL, NULL) == NNP_ERR_ARG, "autotune null");
+    int32_t cfg[3];
+    expect(nnp_get_config(NULL, cfg) == NNP_ERR_ARG, "get_config null");
     expect(strcmp(nnp_last_error(NULL), "null context") == 0, "last_error null");
     for (int s = 0; s <= 7; ++s) expect(nnp_status_string((nnp_status)s) != NULL, "status string");
     nnp_destroy(NULL);

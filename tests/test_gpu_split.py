@@ -200,3 +200,36 @@ def test_split_langevin_graph_equals_eager(make_system):
             out.append(ctx.get_state())
     assert np.array_equal(out[0]["pos"], out[1]["pos"])
     assert np.array_equal(out[0]["vel"], out[1]["vel"])
+
+
+def _expected_default_tile(species, dtype, ncu):
+    """The documented default of the fused path: the smallest of 8, 10, 12-15
+    (16 with the BF16 networks) atoms per tile that gives one workgroup per
+    CU, else the one of 10, 12-15 (16) with the fewest rounds of one tile per
+    CU times (21 + T) microseconds."""
+    tmax = 16 if dtype in ("bf16", "bf16x3") else 15
+
+    def tiles(T):
+        return sum(-(-int((species == e).sum()) // T) for e in range(4))
+
+    for T in (8, 10, 12, 13, 14, 15, 16):
+        if T <= tmax and tiles(T) <= ncu:
+            return T
+    cands = [T for T in (10, 12, 13, 14, 15, 16) if T <= tmax]
+    return min(cands, key=lambda T: (-(-tiles(T) // ncu) * (21 + T), cands.index(T)))
+
+
+@pytest.mark.parametrize("name,dtype", [("mol22", "bf16x3"), ("cluster2500", "bf16x3"), ("cluster23k", "bf16x3"),
+                                        ("cluster23k", "fp32"), ("batch256", "bf16x3"), ("batch256", "fp32")])
+def test_default_tile_choice(make_system, name, dtype):
+    """atoms_per_tile 0: the fused path's tile size, chosen when the positions
+    are first set, follows the documented rule for this device's CU count."""
+    import torch
+    s = make_system(name)
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    with _ctx(s, path="fused", dtype=dtype) as ctx:
+        ctx.set_state(s.pos, s.vel)
+        cfg = ctx.config()
+    T = _expected_default_tile(s.species, dtype, ncu)
+    _say("default tile", name, dtype, cfg, "expected", T, "CUs", ncu)
+    assert cfg["path"] == "fused" and cfg["atoms_per_tile"] == T
