@@ -123,8 +123,9 @@ def test_batch_of_tiny_and_ragged_molecules(weights, dtype, path):
     ctx.close()
 
 
-@pytest.mark.parametrize("T", [0, 5, 10, 12, 14, 15])
-def test_capacity_overflow_is_an_error(weights, T):
+@pytest.mark.parametrize("T,dtype", [(0, "fp32"), (5, "fp32"), (10, "fp32"), (12, "fp32"), (14, "fp32"),
+                                     (15, "fp32"), (16, "bf16x3")])
+def test_capacity_overflow_is_an_error(weights, T, dtype):
     """200 atoms packed into a 3 A ball: every atom has ~199 neighbours within
     5.2 A, beyond the 160 radial entries held per atom and the pair-list
     capacity; the evaluation completes with clamped lists and the call
@@ -136,7 +137,7 @@ def test_capacity_overflow_is_an_error(weights, T):
     import paper_2412_18271_amd as P
     pos = synth.rsa_ball(200, 5, density=200 / (4.0 / 3.0 * np.pi * 27.0), d_min=0.3)
     assert np.sqrt(((pos[:, None] - pos[None]) ** 2).sum(-1)).max() < 6.2
-    ctx = _ctx(np.zeros(200, np.int32), weights, dtype="fp32", path="fused", atoms_per_tile=T)
+    ctx = _ctx(np.zeros(200, np.int32), weights, dtype=dtype, path="fused", atoms_per_tile=T)
     with pytest.raises(P.NNPError) as ei:
         ctx.compute(pos)
     _say("overflow:", ei.value)

@@ -47,7 +47,7 @@ def periodic_ref():
     ("box250", "fp32", "fused", 0), ("box250", "fp32", "plain", 0), ("box250", "bf16x3", "fused", 0),
     ("box2500", "fp32", "fused", 0), ("box2500", "bf16x3", "fused", 0),
     # 14-atom tiles: every atom a full shell, the smallest force-merge table
-    ("box2500", "bf16x3", "fused", 14),
+    ("box2500", "bf16x3", "fused", 14), ("box2500", "bf16x3", "fused", 16),
 ])
 def test_periodic_energy_forces_match_oracle(make_system, periodic_ref, name, dtype, path, T):
     s = make_system(name)
