@@ -134,22 +134,26 @@ def test_trajectory_100_steps_matches_oracle(make_system):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "bf16x3"])
-def test_graph_replay_is_bitwise_equal_to_eager(make_system, dtype):
+@pytest.mark.parametrize("name,dtype,steps", [("cluster2500", "bf16", (150, 130)),
+                                               ("cluster2500", "bf16x3", (150, 130)),
+                                               ("batch256", "bf16x3", (120, 60))])
+def test_graph_replay_is_bitwise_equal_to_eager(make_system, name, dtype, steps):
     """Graph-replayed and eagerly launched steps give bitwise equal states,
-    across several blocks of steps (tiles rebalanced by work before each
-    block), and a second run from the same state repeats the first."""
-    s = make_system("cluster2500")
+    across several blocks of steps (tiles rebalanced by work and reordered
+    before each block), and a second run from the same state repeats the
+    first: 10-atom tiles at 2,500 atoms, 16-atom tiles on the 256-molecule
+    batch."""
+    s = make_system(name)
     out = []
     for graph in (False, True, True):
         ctx = _ctx(s, path="fused", dtype=dtype)
         ctx.set_state(s.pos, s.vel)
-        ctx.step(0.5, 150, graph=graph)
-        ctx.step(0.5, 130, graph=graph)
+        for n in steps:
+            ctx.step(0.5, n, graph=graph)
         out.append(ctx.get_state())
         st = ctx.stats()
-        _say("graph", graph, st)
-        assert st["steps"] == 280
+        _say("graph", graph, ctx.config(), st)
+        assert st["steps"] == sum(steps)
         ctx.close()
     for o in out[1:]:
         assert np.array_equal(out[0]["pos"], o["pos"])
