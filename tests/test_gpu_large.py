@@ -134,3 +134,28 @@ def test_batch256_md_per_molecule_energies(make_system):
     _say("  molecule 0 (%d atoms): max|dx| vs oracle %.2e" % (sl.stop - sl.start, dx))
     assert dx <= 1e-3
     ctx.close()
+
+
+def test_batch256_state_after_rebalanced_blocks_matches_oracle(make_system):
+    """All 256 molecules, split BF16, the autotuner's default tiles (16 atoms
+    per workgroup), 180 graph-replayed steps in two blocks: the tiles are
+    rebalanced by recorded work and reordered before each block and the
+    molecules' pair lists are rebuilt along the way, so the final evaluation
+    runs on moved tiles.  The forces and per-molecule energies held in the
+    state equal the oracle's on each molecule alone at the final positions."""
+    import dataclasses
+    s = make_system("batch256")
+    ctx = _ctx(s, dtype="bf16x3", path="fused")
+    ctx.set_state(s.pos, s.vel)
+    ctx.step(0.5, 120, graph=True)
+    ctx.step(0.5, 60, graph=True)
+    st = ctx.get_state()
+    stats, cfg = ctx.stats(), ctx.config()
+    ctx.close()
+    Eo, Eio, Fo = oracle.system_energy_forces(dataclasses.replace(s, pos=st["pos"]))
+    dE = np.abs(st["pot"] - Eo) / np.array([np.abs(Eio[s.molecule(m)]).sum() for m in range(s.n_molecules)])
+    dF = np.abs(st["forces"] - Fo).max()
+    _say("batch256 after 180 steps (%s, %s): max|dF| %.2e max per-molecule |dE|/S %.2e" % (cfg, stats, dF, dE.max()))
+    assert stats["rebuilds"] >= 5
+    assert dF <= TOL_F["bf16x3"]
+    assert dE.max() <= TOL_E_MOL["bf16x3"]
