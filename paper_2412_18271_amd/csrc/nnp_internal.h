@@ -89,6 +89,9 @@ struct FragLayout {
 // its start and written by the workgroup whose arrival count shows that all
 // of them have read it (it writes at its own end, nobody waits); read by
 // every kernel of the next step.
+constexpr int kArriveGroups = 8;      // arrival counters of the integration kernel's two-level count
+constexpr int kArriveGroupMin = 128;  // workgroups from which it counts in two levels
+
 struct StepState {
     int step;          // steps completed
     int age;           // evaluations since the last rebuild
@@ -97,10 +100,14 @@ struct StepState {
     int overflow;      // a capacity (pair list, radial or angular LDS entries) was exceeded
     int nonfinite;     // a non-finite energy or force was produced
     int last_slot;     // step index of the most recent evaluation (ring slot = index % kRing)
-    unsigned started;  // workgroups of the running integration kernel that have read the state
+    unsigned started;  // workgroups (groups of them in large grids) of the running integration kernel
+                       // that have read the state
     int max_ns, max_nr, max_na;  // largest pair-list / radial / angular count seen
     int pad;
     long long n_eval, n_rebuild, n_forced;
+    // arrivals at the running integration kernel per group of workgroups
+    // (workgroup b in group b mod kArriveGroups), counters 128 B apart
+    alignas(128) unsigned arrive[kArriveGroups][32];
 };
 
 // Cell grid of one large molecule (cells of edge >= 5.2 + skin; atoms outside
