@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(1024) void k_cell_build(Sys S)
 {
     if (!rebuild_due(S.st, S.rebuild_every)) return;
     __shared__ int cnt[kCellBuildCells];
-    __shared__ int part[1024];
+    __shared__ int wsum[16];
     const int t = threadIdx.x, nc = S.ncells, n = S.n;
     for (int i = t; i < nc; i += 1024) cnt[i] = 0;
     __syncthreads();
@@ -1065,26 +1065,36 @@ __global__ __launch_bounds__(1024) void k_cell_build(Sys S)
         }
     }
     __syncthreads();
-    const int per = (nc + 1023) / 1024;
-    const int lo = min(t * per, nc), hi = min(lo + per, nc);
+    // exclusive scan of the counts as in k_cell_scan (wave-owned ranges, 64
+    // consecutive cells per round: no LDS bank conflicts, coalesced stores);
+    // the counts become the cells' running fill positions
+    const int wave = t >> 6, lane = t & 63;
+    const int per = (nc + 1023) / 1024 * 64;
+    const int lo = min(wave * per, nc), hi = min(lo + per, nc);
     int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += cnt[i];
-    part[t] = sum;
+    for (int i = lo + lane; i < hi; i += 64) sum += cnt[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if (lane == 0) wsum[wave] = sum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    int run = 0;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int b = lo; b < hi; b += 64) {  // wave-uniform
+        const int i = b + lane;
+        const int v = i < hi ? cnt[i] : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        if (i < hi) {
+            cnt[i] = run + x - v;
+            S.cell_start[i] = run + x - v;
+        }
+        run += __shfl(x, 63);
     }
-    int run = part[t] - sum;
-    for (int i = lo; i < hi; ++i) {
-        const int k = cnt[i];
-        cnt[i] = run;
-        S.cell_start[i] = run;
-        run += k;
-    }
-    if (t == 1023) S.cell_start[nc] = part[1023];
+    if (t == 1023) S.cell_start[nc] = run;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r)
