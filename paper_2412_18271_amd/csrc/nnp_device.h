@@ -985,18 +985,15 @@ __device__ __forceinline__ void pool_plan_wave(const Env* env, int nact, PoolPla
     if (lane == 0) pl.C = C;
 }
 
-// The run of workgroup lane L (R.p < 0 when L has none); w = its atom.
+// The (atom, element pair) group whose run workgroup lane L takes, or -1:
+// the last group whose first lane is <= L (groups without runs share their
+// successor's first lane).  A binary search of dependent LDS reads, so the
+// fused kernel finds it once and keeps it for the adjoint.
 template <int T>
-__device__ __forceinline__ PairRun pool_run(const Env* env, const PoolPlan<T>& pl, int L, int& w)
+__device__ __forceinline__ int pool_group(const PoolPlan<T>& pl, int L)
 {
     constexpr int NG = T * 10;
-    PairRun R;
-    R.p = -1;
-    R.left = 0;
-    w = 0;
-    if (L >= pl.first[NG]) return R;
-    // last group whose first lane is <= L (groups without runs share their
-    // successor's first lane)
+    if (L >= pl.first[NG]) return -1;
     int lo = 0, hi = NG - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1005,7 +1002,19 @@ __device__ __forceinline__ PairRun pool_run(const Env* env, const PoolPlan<T>& p
         else
             hi = mid - 1;
     }
-    const int g = lo;
+    return lo;
+}
+
+// The run of workgroup lane L in group g = pool_group(pl, L) (R.p < 0 when
+// L has none); w = its atom.
+template <int T>
+__device__ __forceinline__ PairRun pool_run(const Env* env, const PoolPlan<T>& pl, int L, int g, int& w)
+{
+    PairRun R;
+    R.p = -1;
+    R.left = 0;
+    w = 0;
+    if (g < 0) return R;
     w = g / 10;
     const int p = g - 10 * w;
     const Env& E = env[w];
@@ -1051,10 +1060,10 @@ __device__ __forceinline__ long long to_fix(float x)
 // zeroed beforehand) receives the row-segment sums (key = group).
 template <int T>
 __device__ __forceinline__ void angular_features_pooled(const Env* env, const PoolPlan<T>& pl,
-                                                        unsigned long long* accI, int tid)
+                                                        unsigned long long* accI, int tid, int g)
 {
     int w;
-    const PairRun R = pool_run<T>(env, pl, tid, w);
+    const PairRun R = pool_run<T>(env, pl, tid, g, w);
     float t[32];
 #pragma unroll
     for (int f = 0; f < 32; ++f) t[f] = 0.f;
@@ -1081,10 +1090,10 @@ __device__ __forceinline__ void angular_store_pooled(const unsigned long long* a
 // atom w.  G holds the dE/dG rows.  bad: a component reached kFixMax.
 template <int T>
 __device__ __forceinline__ void adjoint_angular_pooled(const Sys& S, const Env* env, const PoolPlan<T>& pl,
-                                                       const float* G, unsigned long long* faccA, int tid)
+                                                       const float* G, unsigned long long* faccA, int tid, int g)
 {
     int w;
-    const PairRun R = pool_run<T>(env, pl, tid, w);
+    const PairRun R = pool_run<T>(env, pl, tid, g, w);
     bool bad = false;
     if (R.p >= 0) {
         float gm[32];

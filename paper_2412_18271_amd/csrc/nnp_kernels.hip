@@ -276,7 +276,8 @@ __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, 
     if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
     if (act) radial_features(E, Grow);
     __syncthreads();
-    angular_features_pooled<T>(sm.env, sm.plan, sm.u.accI, tid);
+    const int pg = pool_group<T>(sm.plan, tid);  // kept for the adjoint
+    angular_features_pooled<T>(sm.env, sm.plan, sm.u.accI, tid, pg);
     __syncthreads();
     angular_store_pooled<T>(sm.u.accI, sm.G, tid, NT);
     __syncthreads();
@@ -289,7 +290,7 @@ __device__ __forceinline__ void pooled_tile(const Sys& S, int tb, PooledSmem<T, 
         // the radial forces are computed in the merge itself
         for (int i = tid; i < T * 64; i += NT) sm.u.adj.gr[i] = sm.G[(i >> 6) * kLdG + (i & 63)];
         __syncthreads();
-        adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.u.adj.faccA, tid);
+        adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.u.adj.faccA, tid, pg);
         __syncthreads();
         // merge the tile's forces per receiving atom in the G rows (dE/dG is
         // no longer read)
@@ -378,7 +379,7 @@ __device__ __forceinline__ void desc_tile(const Sys& S, int tb, DescSmem<T>& sm)
     if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
     if (act) radial_features(E, sm.u.d.G + w * kLdG);
     __syncthreads();
-    angular_features_pooled<T>(sm.env, sm.plan, sm.u.d.accI, tid);
+    angular_features_pooled<T>(sm.env, sm.plan, sm.u.d.accI, tid, pool_group<T>(sm.plan, tid));
     __syncthreads();
     angular_store_pooled<T>(sm.u.d.accI, sm.u.d.G, tid, NT);
     __syncthreads();
@@ -436,7 +437,7 @@ __device__ __forceinline__ void adj_tile(const Sys& S, int tb, AdjSmem<T>& sm)
     __syncthreads();
     if (wave == NT / 64 - 1) pool_plan_wave<T, NT>(sm.env, tile.y, sm.plan, lane);
     __syncthreads();
-    adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.faccA, tid);
+    adjoint_angular_pooled<T>(S, sm.env, sm.plan, sm.G, sm.faccA, tid, pool_group<T>(sm.plan, tid));
     __syncthreads();
     const ForceTable ft = force_table(sm.G, sizeof(sm.G) + sizeof(sm.Gx));
     table_clear(ft, tid, NT);
@@ -721,7 +722,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_integrate(Sys S, doub
     if (lane == 0) seen[tid >> 6] = nstep ^ age ^ valid ^ (int)rb ^ (int)ne ^ prev_slot;
     __syncthreads();
     if (tid == 0) {
-        if (gridDim.x < kArriveGroupMin) {
+        // the grid is one workgroup per kGatherThreads atoms (the launcher's),
+        // so the count's form follows from n, read with the other arguments
+        // at entry (gridDim is a separate load on the way to the atomic)
+        if (S.n <= (kArriveGroupMin - 1) * kGatherThreads) {
             const unsigned prev = __hip_atomic_fetch_add(&st->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             last = prev == gridDim.x - 1;
         } else {
