@@ -289,6 +289,12 @@ def batch_leg(P, steps, warmup):
         rs = rate_summary(secs, steps, M)
         out["batched_molecule_steps_per_s"] = rs["rate"]
         out["batched_spread"] = rs["spread"]
+        try:
+            ctx.get_state()  # synchronising: raises on the sticky device flags
+            out["within_capacity"] = True
+        except P.NNPError as e:
+            out["within_capacity"] = False
+            out["capacity_error"] = str(e)
     finally:
         ctx.close()
     ctxs = []
@@ -545,9 +551,13 @@ def cpu_baseline(s, seconds):
             "single_core_value": one}
 
 
-def nve_energies(ctx, s, n, chunk=2000):
+def nve_energies(P, ctx, s, n, chunk=500):
     """H = U + K at every step of an n-step NVE run from the initial state
-    (the device keeps the last 4096 steps; read after every chunk)."""
+    (the device keeps the last 4096 steps; read after every chunk).  The
+    device flags are checked after every chunk: the run stops at the first
+    chunk in which an atom's environment exceeded the library's capacity
+    (or a result was not finite), and only the steps before that chunk are
+    returned, with the error."""
     ctx.set_state(s.pos, s.vel)
     H = []
     done = 0
@@ -555,9 +565,13 @@ def nve_energies(ctx, s, n, chunk=2000):
         c = min(chunk, n - done)
         ctx.step(DT_FS, c, graph=True)
         U, K = ctx.energy_log(c + 1 if done == 0 else c)
+        try:
+            ctx.get_state()  # synchronising: raises on the sticky device flags
+        except P.NNPError as e:
+            return (np.concatenate(H) if H else np.zeros(0)), done, str(e)
         H.append(U[:, 0] + K[:, 0])
         done += c
-    return np.concatenate(H)
+    return np.concatenate(H), done, None
 
 
 def precision_study(P, steps_drift):
@@ -591,15 +605,15 @@ def precision_study(P, steps_drift):
                      "max_force_err": float(np.abs(F[sel] - Fo[sel]).max()),
                      "rms_force_err": float(np.sqrt(np.mean((F[sel] - Fo[sel]) ** 2))),
                      "force_atoms_checked": int(len(sel))}
-                n = steps_drift
-                t0 = time.perf_counter()
-                H = nve_energies(ctx, s, n)
-                r["drift_steps"] = n
-                r["drift_steps_per_s"] = n / (time.perf_counter() - t0)
-                t = np.arange(H.shape[0]) * DT_FS * 1e-3
-                r["drift_max_abs_eV"] = float(np.max(np.abs(H - H[0])))
-                r["drift_slope_meV_per_atom_ps"] = float(np.polyfit(t, H, 1)[0] * 1e3 / s.n_atoms)
+                H, n, err = nve_energies(P, ctx, s, steps_drift)
                 r["stats"] = ctx.stats()
+                r["drift_steps"] = n  # steps with every environment within capacity
+                if err is not None:
+                    r["drift_stopped"] = err
+                if n >= 2:
+                    t = np.arange(H.shape[0]) * DT_FS * 1e-3
+                    r["drift_max_abs_eV"] = float(np.max(np.abs(H - H[0])))
+                    r["drift_slope_meV_per_atom_ps"] = float(np.polyfit(t, H, 1)[0] * 1e3 / s.n_atoms)
             except Exception as e:  # report the failure for this dtype
                 r = {"error": str(e)}
             finally:
