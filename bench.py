@@ -564,9 +564,8 @@ def nve_energies(P, ctx, s, n, chunk=500):
     while done < n:
         c = min(chunk, n - done)
         ctx.step(DT_FS, c, graph=True)
-        U, K = ctx.energy_log(c + 1 if done == 0 else c)
         try:
-            ctx.get_state()  # synchronising: raises on the sticky device flags
+            U, K = ctx.energy_log(c + 1 if done == 0 else c)  # raises on the sticky device flags
         except P.NNPError as e:
             return (np.concatenate(H) if H else np.zeros(0)), done, str(e)
         H.append(U[:, 0] + K[:, 0])

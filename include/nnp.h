@@ -305,14 +305,18 @@ nnp_status nnp_set_thermostat(nnp_context* ctx, double temperature_K, double fri
 
 /* Potential and kinetic energy of the last min(count, steps done, ring size)
  * steps, oldest first: U and K are [count][n_molecules] double.  Returns the
- * number of steps written in *written.  The ring holds 4096 steps. */
+ * number of steps written in *written.  The ring holds 4096 steps.  Like
+ * nnp_get_state, returns NNP_ERR_STATE (a capacity was exceeded) or
+ * NNP_ERR_NONFINITE when a step since the flags were last clear produced
+ * such a result, writing nothing (*written = 0). */
 nnp_status nnp_energy_log(nnp_context* ctx, int32_t count, double* U, double* K, int32_t* written);
 
 /* Counters since creation: [0] evaluations, [1] pair-list rebuilds, [2] rebuilds
  * forced by displacement > skin/2, [3] steps, [4] longest pair list, [5] most
  * neighbours within 5.2 A, [6] most neighbours within 3.5 A (capacities: 256,
- * 160 and 96 per atom; exceeding one makes the next synchronising call return
- * NNP_ERR_STATE).  stats is int64[7]. */
+ * 160 and 96 per atom; exceeding one makes nnp_compute, nnp_get_state,
+ * nnp_energy_log and the timing calls return NNP_ERR_STATE from then on,
+ * while nnp_stats keeps reporting these counters).  stats is int64[7]. */
 nnp_status nnp_stats(nnp_context* ctx, int64_t* stats);
 
 /* The kernel configuration in use: config[0] path (nnp_path), [1] atoms per

@@ -1530,7 +1530,12 @@ nnp_status nnp_get_state(nnp_context* c, double* pos, double* vel, double* force
 nnp_status nnp_energy_log(nnp_context* c, int32_t count, double* U, double* K, int32_t* written)
 {
     if (!c || !U || !K || !written || count < 0) return fail(c, NNP_ERR_ARG, "bad arguments");
+    *written = 0;
     HIP_TRY(c, launch_energy_flush(c->S, c->stream));
+    // energies of steps whose environments were clamped (or not finite) are
+    // not handed out: the sticky device flags are reported here too
+    const nnp_status f = check_device_flags(c);
+    if (f != NNP_OK) return f;
     StepState st;
     HIP_TRY(c, hipMemcpyAsync(&st, c->S.st, sizeof st, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

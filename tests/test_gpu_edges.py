@@ -145,6 +145,26 @@ def test_capacity_overflow_is_an_error(weights, T, dtype):
     ctx.close()
 
 
+def test_capacity_overflow_during_md_is_reported(weights):
+    """The same packed ball advanced by MD steps: the steps themselves only
+    enqueue work, and the energy log and the state then refuse to hand out
+    results computed on clamped environments (NNP_ERR_STATE), while the
+    counters still show the observed maxima."""
+    import paper_2412_18271_amd as P
+    pos = synth.rsa_ball(200, 5, density=200 / (4.0 / 3.0 * np.pi * 27.0), d_min=0.3)
+    ctx = _ctx(np.zeros(200, np.int32), weights, dtype="bf16x3", path="fused")
+    ctx.set_state(pos, np.zeros_like(pos))
+    ctx.step(0.5, 3, graph=True)
+    for call in (lambda: ctx.energy_log(4), ctx.get_state):
+        with pytest.raises(P.NNPError) as ei:
+            call()
+        assert ei.value.status == 6 and "capacity exceeded" in str(ei.value), ei.value
+    st = ctx.stats()
+    _say("overflow in MD:", st)
+    assert st["max_radial"] > 160 and st["steps"] == 3
+    ctx.close()
+
+
 @pytest.mark.parametrize("path", ["fused", "plain"])
 def test_invalid_positions_are_rejected_and_context_recovers(weights, path):
     """NaN or infinite coordinates and two atoms at one point are rejected on
