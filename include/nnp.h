@@ -248,7 +248,7 @@ nnp_status nnp_get_state(nnp_context* ctx, double* pos, double* vel, double* for
 nnp_status nnp_step(nnp_context* ctx, double dt_fs, int32_t n_steps, int32_t use_graph);
 
 /* Captures and instantiates the HIP graphs that nnp_step(ctx, dt_fs, n_steps,
- * 1) replays (one per block length: min(n_steps, 100) and the remainder),
+ * 1) replays (one per block length: min(n_steps, 200) and the remainder),
  * without running any step, so that a following nnp_step with the same
  * arguments replays cached graphs only (serving loops, timed regions).
  * The state is unchanged.  NNP_ERR_STATE on the null stream or with extra

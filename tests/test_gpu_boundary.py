@@ -79,7 +79,8 @@ def test_energy_only_device_call_rejects_forces(make_system):
 
 def test_capture_then_step_replays_same_trajectory(make_system):
     """nnp_capture changes no state; steps replayed from the pre-captured
-    graphs equal eager steps bitwise (blocks of 100 and a remainder)."""
+    graphs equal eager steps bitwise (a block of 200 and a remainder of
+    130: two graphs, and the tiles rebalanced between them)."""
     s = make_system("cluster2500")
     out = []
     for mode in ("eager", "captured"):
@@ -88,14 +89,14 @@ def test_capture_then_step_replays_same_trajectory(make_system):
         ctx.step(0.5, 5, graph=mode == "captured")
         if mode == "captured":
             before = ctx.get_state()
-            ctx.capture(0.5, 130)
+            ctx.capture(0.5, 330)
             after = ctx.get_state()
             for k in ("pos", "vel", "forces"):
                 assert np.array_equal(before[k], after[k])
             assert ctx.stats()["steps"] == 5
-        ctx.step(0.5, 130, graph=mode == "captured")
+        ctx.step(0.5, 330, graph=mode == "captured")
         out.append(ctx.get_state())
-        assert ctx.stats()["steps"] == 135
+        assert ctx.stats()["steps"] == 335
         ctx.close()
     for k in ("pos", "vel", "forces"):
         assert np.array_equal(out[0][k], out[1][k])
