@@ -118,6 +118,13 @@ struct nnp_context {
     // pinned staging
     double* h_stage = nullptr;
     size_t h_stage_bytes = 0;
+    // tile rebalancing: the recorded work read back and the new tile tables
+    // uploaded through pinned memory (allocated on first use)
+    int* h_work = nullptr;
+    int4* h_tiles = nullptr;
+    int* h_atoms = nullptr;
+    int* h_tmol = nullptr;
+    size_t reb_n = 0, reb_nt = 0;  // atoms and tiles these buffers hold
 };
 
 namespace {
@@ -261,12 +268,12 @@ std::vector<int4> make_tiles(const std::vector<int>& elem, int T)
 // a cell grid and has at most kSharedScanCap atoms, else -1 (each atom then
 // scans for itself).  Needed whenever the tiles' atoms or the grids change.
 // Synchronous.
-nnp_status upload_tile_mol(nnp_context* c)
+// tile_mol entry of every tile (host tables); false before they exist.
+bool tile_mol_table(const nnp_context* c, int* tm)
 {
     if (c->tiles.empty() || c->molgrid.size() != (size_t)c->nmol || c->perm.size() != (size_t)c->n ||
         c->tile_atoms.size() != c->tiles.size() * kTileCap)
-        return NNP_OK;
-    std::vector<int> tm(c->tiles.size(), -1);
+        return false;
     for (size_t b = 0; b < c->tiles.size(); ++b) {
         const int* col = c->tile_atoms.data() + b * kTileCap;
         const int m = c->mol_of[c->perm[col[0]]];
@@ -274,6 +281,13 @@ nnp_status upload_tile_mol(nnp_context* c)
         for (int i = 1; i < c->tiles[b].y && one; ++i) one = c->mol_of[c->perm[col[i]]] == m;
         tm[b] = one ? m : -1;
     }
+    return true;
+}
+
+nnp_status upload_tile_mol(nnp_context* c)
+{
+    std::vector<int> tm(c->tiles.size(), -1);
+    if (!tile_mol_table(c, tm.data())) return NNP_OK;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipMemcpy((void*)c->S.tile_mol, tm.data(), sizeof(int) * tm.size(), hipMemcpyHostToDevice));
     return NNP_OK;
@@ -306,12 +320,38 @@ bool balanced_tiles(const nnp_context* c)
     return (c->path == NNP_PATH_FUSED && (c->T == 5 || c->T >= 10)) || c->path == NNP_PATH_SPLIT;
 }
 
+void free_rebalance_buffers(nnp_context* c)
+{
+    if (c->h_work) (void)hipHostFree(c->h_work);
+    if (c->h_tiles) (void)hipHostFree(c->h_tiles);
+    if (c->h_atoms) (void)hipHostFree(c->h_atoms);
+    if (c->h_tmol) (void)hipHostFree(c->h_tmol);
+    c->h_work = c->h_atoms = c->h_tmol = nullptr;
+    c->h_tiles = nullptr;
+    c->reb_n = c->reb_nt = 0;
+}
+
+// The device stays idle while the tiles are rebalanced between blocks, so
+// the read-back and the uploads go through pinned buffers, and the uploads
+// are left in flight: the graph launch that follows is ordered after them,
+// and the next rebalancing synchronises the stream before it rewrites the
+// buffers.
 nnp_status rebalance_tiles(nnp_context* c)
 {
     if (!balanced_tiles(c) || !c->laid_out) return NNP_OK;
     const int n = c->n, nt = (int)c->tiles.size();
-    std::vector<int> work(n);
-    HIP_TRY(c, hipMemcpyAsync(work.data(), c->S.work, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+    if (c->reb_n != (size_t)n || c->reb_nt != (size_t)nt) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        free_rebalance_buffers(c);
+        HIP_TRY(c, hipHostMalloc((void**)&c->h_work, sizeof(int) * n));
+        HIP_TRY(c, hipHostMalloc((void**)&c->h_tiles, sizeof(int4) * nt));
+        HIP_TRY(c, hipHostMalloc((void**)&c->h_atoms, sizeof(int) * nt * kTileCap));
+        HIP_TRY(c, hipHostMalloc((void**)&c->h_tmol, sizeof(int) * nt));
+        c->reb_n = n;
+        c->reb_nt = nt;
+    }
+    int* work = c->h_work;
+    HIP_TRY(c, hipMemcpyAsync(work, c->S.work, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     bool changed = false;
     for (int e = 0; e < kNumSpecies; ++e) {
@@ -374,13 +414,16 @@ nnp_status rebalance_tiles(nnp_context* c)
         c->tile_atoms.swap(atoms2);
     }
     if (changed) {
-        HIP_TRY(c, hipMemcpyAsync((void*)c->S.tiles, c->tiles.data(), sizeof(int4) * c->tiles.size(),
+        std::copy(c->tiles.begin(), c->tiles.end(), c->h_tiles);
+        std::copy(c->tile_atoms.begin(), c->tile_atoms.end(), c->h_atoms);
+        HIP_TRY(c, hipMemcpyAsync((void*)c->S.tiles, c->h_tiles, sizeof(int4) * nt, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync((void*)c->S.tile_atoms, c->h_atoms, sizeof(int) * (size_t)nt * kTileCap,
                                   hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, hipMemcpyAsync((void*)c->S.tile_atoms, c->tile_atoms.data(), sizeof(int) * c->tile_atoms.size(),
-                                  hipMemcpyHostToDevice, c->stream));
+        if (tile_mol_table(c, c->h_tmol))
+            HIP_TRY(c, hipMemcpyAsync((void*)c->S.tile_mol, c->h_tmol, sizeof(int) * nt, hipMemcpyHostToDevice,
+                                      c->stream));
     }
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return changed ? upload_tile_mol(c) : NNP_OK;
+    return NNP_OK;
 }
 
 // Cell grids of the molecules with more than kBruteMax atoms (the others scan
@@ -1128,6 +1171,7 @@ void nnp_destroy(nnp_context* c)
         if (g_static[c->static_dev].owner == c) g_static[c->static_dev].owner = nullptr;
     }
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_rebalance_buffers(c);
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& b : c->bufs) (void)hipFree(b.p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
